@@ -1,0 +1,166 @@
+"""Plain FP64 definitions of the three workloads of section 7, unfused.
+
+Test infrastructure only.  Each function performs the same elementwise
+steps, in the same order, as the task stream the fused path executes, and
+materialises every intermediate as a full array.  Transcendentals call the
+host C library (oracle/cnum.c); reductions are exactly rounded.
+
+  black_scholes  European call and put prices with an erf-based normal CDF
+                 (section 7's Black-Scholes benchmark; the paper gives no
+                 formula, so the standard closed form is used):
+                   d1 = (ln(S/K) + (r + sigma^2/2) T) / (sigma sqrt(T))
+                   d2 = d1 - sigma sqrt(T)
+                   N(x) = (erf(x / sqrt(2)) + 1) / 2
+                   call = S N(d1) - K e^{-rT} N(d2)
+                   put  = K e^{-rT} (1 - N(d2)) - S (1 - N(d1))
+  jacobi_sweep   one sweep of the 5-point stencil of section 2 (the
+                 motivating example): work = 0.2 (c + n + e + w + s) over the
+                 interior, the squared-difference residual sum(work - c)^2,
+                 then center <- work
+  cg             conjugate gradient (Hestenes-Stiefel) as issued by the
+                 sparse Krylov benchmark of section 7: q = A p, alpha = rho/(p.q),
+                 x += alpha p, r -= alpha q, rho' = r.r, beta = rho'/rho,
+                 p = beta p + r
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import cnum
+
+INV_SQRT2 = 0.70710678118654752440  # 1/sqrt(2) rounded to double
+
+
+def bs_scalars(r: float, sigma: float, dtype=np.float64):
+    """The broadcast scalars the stream reads: r, sigma and r + sigma^2/2.
+
+    For a float32 stream they are rounded to float32 (each rounding of the
+    float32 evaluation of r + 0.5*sigma*sigma); the oracle then computes with
+    their exact values in float64."""
+    if dtype == np.float32:
+        f = np.float32
+        r32, s32 = f(r), f(sigma)
+        rv = f(r32 + f(f(0.5) * f(s32 * s32)))
+        return float(r32), float(s32), float(rv)
+    rv = r + 0.5 * (sigma * sigma)
+    return r, sigma, rv
+
+
+def black_scholes(S, K, T, r, sigma, rv, c=INV_SQRT2):
+    """Call and put prices, each step one materialised FP64 array."""
+    S = np.asarray(S, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    sqrtT = np.sqrt(T)
+    vs = sqrtT * sigma
+    SK = S / K
+    lnSK = cnum.log(SK)
+    A = T * rv
+    B = lnSK + A
+    d1 = B / vs
+    d2 = d1 - vs
+    e1 = d1 * c
+    f1 = cnum.erf(e1)
+    g1 = f1 + 1.0
+    N1 = g1 * 0.5
+    e2 = d2 * c
+    f2 = cnum.erf(e2)
+    g2 = f2 + 1.0
+    N2 = g2 * 0.5
+    rT = T * r
+    nrT = -rT
+    disc = cnum.exp(nrT)
+    Kd = K * disc
+    SN1 = S * N1
+    KN2 = Kd * N2
+    call = SN1 - KN2
+    oN2 = 1.0 - N2
+    oN1 = 1.0 - N1
+    KoN2 = Kd * oN2
+    SoN1 = S * oN1
+    put = KoN2 - SoN1
+    return call, put
+
+
+def jacobi_sweep(grid):
+    """One sweep on a full (N, N) grid in place; returns sum((work-c)^2) exactly rounded."""
+    c = grid[1:-1, 1:-1]
+    n = grid[0:-2, 1:-1]
+    s = grid[2:, 1:-1]
+    w = grid[1:-1, 0:-2]
+    e = grid[1:-1, 2:]
+    t1 = c + n
+    t2 = t1 + e
+    t3 = t2 + w
+    avg = t3 + s
+    work = avg * 0.2
+    d = work - c
+    ss = cnum.fsum_prod(d, d)
+    grid[1:-1, 1:-1] = work
+    return ss
+
+
+def jacobi(grid, sweeps):
+    """`sweeps` sweeps in place; returns the list of residual norms sqrt(ss)."""
+    res = []
+    for _ in range(sweeps):
+        res.append(math.sqrt(jacobi_sweep(grid)))
+    return res
+
+
+def jacobi_naive(grid, sweeps):
+    """The same sweeps written as plain double loops with no views.
+
+    Pure Python: tiny grids only."""
+    g = [list(map(float, row)) for row in np.asarray(grid)]
+    N = len(g)
+    res = []
+    for _ in range(sweeps):
+        work = [[0.0] * N for _ in range(N)]
+        sq = []
+        for i in range(1, N - 1):
+            for j in range(1, N - 1):
+                t = g[i][j] + g[i - 1][j]
+                t = t + g[i][j + 1]
+                t = t + g[i][j - 1]
+                t = t + g[i + 1][j]
+                wv = t * 0.2
+                work[i][j] = wv
+                d = wv - g[i][j]
+                sq.append(d * d)
+        for i in range(1, N - 1):
+            for j in range(1, N - 1):
+                g[i][j] = work[i][j]
+        res.append(math.sqrt(math.fsum(sq)))
+    return np.array(g), res
+
+
+def cg(rowptr, col, val, b, iters, tol=None):
+    """Conjugate gradient from x0 = 0.
+
+    Returns (x, rho_history) where rho_history[k] = r_k . r_k (k = 0..done).
+    With `tol`, stops once sqrt(rho_k) <= tol * ||b||."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rho = cnum.fsum_prod(r, r)
+    hist = [rho]
+    bnorm = math.sqrt(rho)
+    for _ in range(iters):
+        if tol is not None and math.sqrt(rho) <= tol * bnorm:
+            break
+        q = cnum.spmv(rowptr, col, val, p)
+        pq = cnum.fsum_prod(p, q)
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_new = cnum.fsum_prod(r, r)
+        beta = rho_new / rho
+        rho = rho_new
+        p = beta * p
+        p = p + r
+        hist.append(rho)
+    return x, hist
