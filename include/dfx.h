@@ -1,0 +1,226 @@
+/*
+ * dfx -- fused execution of task windows over logical arrays on AMD MI355X.
+ *
+ * The calls follow the statement of the problem in "Composing Distributed
+ * Computations Through Task and Kernel Fusion" (Yadav et al., ASPLOS 2025):
+ *
+ *   - stores, projection functions, partitions, privileges and index tasks
+ *     are the IR of section 3 (the syntax figure of section 3, data model in
+ *     section 3.1, computational model in section 3.2);
+ *   - submitted tasks are buffered in a task window and a fusible prefix is
+ *     found with the four fusion constraints of section 4.2;
+ *   - stores made temporary by fusion (section 5.1) get no device memory;
+ *     application references are counted separately from references held by
+ *     pending tasks (split reference counts, section 5.1);
+ *   - analysis and the executable plan are memoised on the canonical form of
+ *     the window (section 5.2);
+ *   - flush and release are the `flush_window` and `del` of section 5.1.
+ *
+ * Conventions
+ *   Every call returns int: DFX_OK (0) or a negative DFX_E* code; the text of
+ *   the last error is available from dfx_last_error(ctx).  A rejected call
+ *   changes nothing (a rejected submit leaves the window as it was).  A
+ *   context is used from one host thread at a time.  Host buffers passed in
+ *   remain owned by the caller and are copied before the call returns.
+ *   Device memory of stores is owned by the library (allocated through the
+ *   configured callbacks, default a stream-ordered hipMallocAsync pool),
+ *   except for stores made with dfx_store_wrap, whose memory is borrowed and
+ *   never freed.  Handles are never reused within a context.
+ */
+#ifndef DFX_H
+#define DFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DFX_MAX_DIM 4
+
+enum {
+  DFX_OK = 0,
+  DFX_EINVAL = -1,        /* malformed call, illegal task, shape/partition mismatch */
+  DFX_ENOMEM = -2,        /* device or host allocation failed */
+  DFX_EHIP = -3,          /* a HIP runtime call failed */
+  DFX_ESTATE = -4,        /* call not valid in the current state (e.g. values in an analysis-only context) */
+  DFX_ENOMEM_BUDGET = -5, /* a serving request can never fit the HBM budget */
+  DFX_EBREAKDOWN = -6,    /* CG breakdown (p.q <= 0 or non-finite) */
+  DFX_EMAXITER = -7,      /* iteration limit reached before the tolerance */
+  DFX_ENOTFOUND = -8,     /* unknown handle or ticket */
+  DFX_EUNSUPPORTED = -9   /* legal in the IR but not executable by this library */
+};
+
+typedef int64_t dfx_store;   /* store handle (section 3.1: Store(id, shape)) */
+typedef int32_t dfx_part;    /* interned partition handle */
+typedef int32_t dfx_proj;    /* interned projection-function handle */
+typedef struct dfx_ctx dfx_ctx;
+
+typedef enum { DFX_F32 = 0, DFX_F64 = 1, DFX_I32 = 2, DFX_I64 = 3 } dfx_dtype;
+
+/* Privileges of section 3.2: read, write, read-write, reduce (one operator, +). */
+typedef enum { DFX_R = 1, DFX_W = 2, DFX_RW = 3, DFX_RD = 4 } dfx_priv;
+
+/*
+ * Operation table.  Each op lists its arguments in order with the privilege
+ * each must carry; k is imm[0].  All floating arguments of one task share one
+ * dtype (F32 or F64); arithmetic is in that dtype with IEEE rounding of every
+ * operation (no contraction into fused multiply-adds).
+ *   unary  (a R, out W):     NEG ABS SQRT EXP LOG ERF SQUARE(a*a) COPY
+ *   binary (a R, b R, out W): ADD SUB MUL DIV POW MAX MIN
+ *   immediate (a R, out W):  ADD_IMM a+k  SUB_IMM a-k  RSUB_IMM k-a
+ *                            MUL_IMM a*k  DIV_IMM a/k  RDIV_IMM k/a
+ *   FILL (out W):            out = k
+ *   AXPY (alpha R, x R, y RW): y = y + alpha*x if k >= 0, y = y - alpha*x if k < 0
+ *   SUM   (x R, s Rd)        s = s + sum(x)          (s = sum(x) if k != 0)
+ *   SUMSQ (x R, s Rd)        s = s + sum(x*x)        (init flag as SUM)
+ *   DOT   (x R, y R, s Rd)   s = s + sum(x*y)        (init flag as SUM)
+ *   SPMV_CSR (rowptr R, col R, val R, x R, y W): y = A x for the rows of y's
+ *            sub-store; rowptr/col are I32, val/x/y floating; each row is
+ *            summed sequentially in CSR order.
+ * Reductions produce a 0-d store through the None partition with privilege
+ * Rd.  The sum's rounding order is a fixed tree determined only by the
+ * element index (so fused and unfused execution agree bit for bit).
+ */
+typedef enum {
+  DFX_OP_NEG = 1, DFX_OP_ABS, DFX_OP_SQRT, DFX_OP_EXP, DFX_OP_LOG, DFX_OP_ERF,
+  DFX_OP_SQUARE, DFX_OP_COPY,
+  DFX_OP_ADD = 16, DFX_OP_SUB, DFX_OP_MUL, DFX_OP_DIV, DFX_OP_POW, DFX_OP_MAX, DFX_OP_MIN,
+  DFX_OP_ADD_IMM = 32, DFX_OP_SUB_IMM, DFX_OP_RSUB_IMM, DFX_OP_MUL_IMM, DFX_OP_DIV_IMM,
+  DFX_OP_RDIV_IMM,
+  DFX_OP_FILL = 48, DFX_OP_AXPY,
+  DFX_OP_SUM = 64, DFX_OP_SUMSQ, DFX_OP_DOT,
+  DFX_OP_SPMV_CSR = 80
+} dfx_op;
+
+/* Device allocation callbacks: return NULL on failure.  `stream` is the
+ * context's hipStream_t; frees are stream-ordered. */
+typedef void* (*dfx_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*dfx_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
+typedef struct {
+  int32_t device;        /* HIP device ordinal; -1 = analysis-only context (no GPU, no values) */
+  void* stream;          /* hipStream_t all work is ordered on (NULL: the null stream) */
+  dfx_alloc_fn alloc;    /* NULL: hipMallocAsync on `stream` */
+  dfx_free_fn dealloc;   /* NULL: hipFreeAsync on `stream` */
+  void* alloc_user;
+  int32_t window_size;   /* tasks buffered before analysis runs (>= 1) */
+  int32_t fuse;          /* 0: unfused baseline, one task per launch, every store materialised */
+  int32_t memo;          /* 1: memoise analysis and plan on the window's canonical form */
+  int32_t reserved[9];
+} dfx_config;
+
+typedef struct {
+  dfx_store store;
+  dfx_part part;
+  int32_t priv;          /* dfx_priv */
+} dfx_arg;
+
+/* IndexTask(domain, [(S, P, Pr)]) of section 3.2; ndim = 0 is a single task. */
+typedef struct {
+  uint32_t op;           /* dfx_op */
+  int32_t ndim;          /* launch-domain rank, 0..DFX_MAX_DIM */
+  const int64_t* launch; /* launch-domain extents (ndim entries, each >= 1) */
+  int32_t nargs;
+  const dfx_arg* args;
+  int32_t nimm;
+  const double* imm;
+} dfx_task;
+
+typedef struct {
+  int64_t tasks_submitted;
+  int64_t tasks_dispatched;
+  int64_t groups_dispatched;     /* fused tasks issued (one per analysed prefix) */
+  int64_t launches;              /* kernel launches (graph replays count their nodes) */
+  int64_t temporaries_eliminated;
+  int64_t memo_hits;
+  int64_t memo_misses;
+  int64_t graph_replays;
+  int64_t alg_bytes;             /* algorithmic HBM bytes of everything launched */
+  double analysis_seconds;       /* host time in analysis + lowering (misses only) */
+} dfx_stats;
+
+#define DFX_INFO_MAX 64
+typedef struct {
+  int64_t first_task;            /* sequence number (0-based) of the group's first task */
+  int32_t prefix_len;            /* tasks fused into this group */
+  int32_t memo_hit;
+  int32_t n_passes;              /* kernel launches for the group */
+  int32_t pass_kind[8];          /* 0 elementwise/reduction, 1 SpMV, 2 single task */
+  int32_t n_temporaries;
+  dfx_store temporaries[DFX_INFO_MAX];
+  int64_t alg_bytes;             /* algorithmic bytes of the group's launches */
+} dfx_group_info;
+
+/* ---- context ---------------------------------------------------------- */
+/* Section 4 (task window) and the configuration above.  Destroy flushes. */
+int dfx_create(const dfx_config* cfg, dfx_ctx** out);
+int dfx_destroy(dfx_ctx* ctx);
+const char* dfx_last_error(dfx_ctx* ctx);
+const char* dfx_version(void);
+
+/* ---- stores (section 3.1) --------------------------------------------- */
+/* Create a store of the given shape (ndim 0 = scalar).  Memory is allocated
+ * lazily, when a dispatched task first writes it or on dfx_store_write; the
+ * application reference count starts at 1. */
+int dfx_store_create(dfx_ctx* ctx, int32_t ndim, const int64_t* shape, int32_t dtype,
+                     dfx_store* out);
+/* Borrow C-contiguous device memory `dptr` as a store (never freed). */
+int dfx_store_wrap(dfx_ctx* ctx, void* dptr, int32_t ndim, const int64_t* shape,
+                   int32_t dtype, dfx_store* out);
+/* Copy `bytes` (= the store's full size) from host memory into the store.
+ * Flushes the window first. */
+int dfx_store_write(dfx_ctx* ctx, dfx_store s, const void* host, size_t bytes);
+/* Flush, synchronise, copy the whole store to host memory. */
+int dfx_store_read(dfx_ctx* ctx, dfx_store s, void* host, size_t bytes);
+/* Flush and return the store's device address (allocating it if needed). */
+int dfx_store_device_ptr(dfx_ctx* ctx, dfx_store s, void** dptr);
+/* Drop the application's reference (Python `del`, section 5.1). */
+int dfx_store_release(dfx_ctx* ctx, dfx_store s);
+
+/* ---- projections and partitions (section 3.1) -------------------------- */
+int dfx_proj_identity(dfx_ctx* ctx, int32_t ndim, dfx_proj* out);
+/* Point -> Point keeping the launch dims whose bits are set in keep_mask, in
+ * increasing order (e.g. ndim_in=2, mask=0b10 maps (i, j) to (j)). */
+int dfx_proj_drop(dfx_ctx* ctx, int32_t ndim_in, uint32_t keep_mask, dfx_proj* out);
+/* None: every point maps to the whole store (replication). */
+int dfx_part_none(dfx_ctx* ctx, dfx_part* out);
+/* Tiling(tile, offset, proj): point p maps to [proj(p)*tile, proj(p+1)*tile) + offset
+ * (the sub-store-bounds formula of section 3.1); ndim is the store's rank. */
+int dfx_part_tiling(dfx_ctx* ctx, int32_t ndim, const int64_t* tile, const int64_t* offset,
+                    dfx_proj proj, dfx_part* out);
+/* Image(src, src_part): the entries named by the coordinates stored in
+ * src[src_part, p] (the gathered operand of a sparse product).  Never equal
+ * to a None or Tiling partition. */
+int dfx_part_image(dfx_ctx* ctx, dfx_store src, dfx_part src_part, dfx_part* out);
+
+/* ---- tasks ------------------------------------------------------------ */
+/* Validate and append an index task to the window; when the window holds
+ * window_size tasks, analyse it and dispatch its longest fusible prefix. */
+int dfx_submit(dfx_ctx* ctx, const dfx_task* task);
+/* Analyse and dispatch until the window is empty (flush_window, section 5.1). */
+int dfx_flush(dfx_ctx* ctx);
+/* Flush and wait for all dispatched work. */
+int dfx_sync(dfx_ctx* ctx);
+
+/* ---- whole-region graphs ----------------------------------------------- */
+/* Flush, then record every launch dispatched until dfx_graph_end into one
+ * hipGraph.  No store may need new memory while recording (DFX_ESTATE). */
+int dfx_graph_begin(dfx_ctx* ctx);
+int dfx_graph_end(dfx_ctx* ctx, int32_t* graph_id);
+/* Replay a recorded region on the context's stream (same stores, same order). */
+int dfx_graph_launch(dfx_ctx* ctx, int32_t graph_id);
+int dfx_graph_destroy(dfx_ctx* ctx, int32_t graph_id);
+
+/* ---- introspection ---------------------------------------------------- */
+int dfx_stats_get(dfx_ctx* ctx, dfx_stats* out);
+int dfx_stats_reset(dfx_ctx* ctx);
+/* Number of groups recorded since the last reset, and the i-th one. */
+int dfx_group_count(dfx_ctx* ctx, int64_t* n);
+int dfx_group_get(dfx_ctx* ctx, int64_t i, dfx_group_info* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFX_H */

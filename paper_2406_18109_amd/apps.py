@@ -1,0 +1,150 @@
+"""Task streams of the three workloads of section 7, issued through the binding.
+
+These play the part of the application (the NumPy/SciPy-style program whose
+library calls become index tasks): each function submits tasks and drops its
+references to intermediates the way Python name rebinding would, so the
+library's temporary analysis sees the same reference state the paper's
+runtime would.  No arithmetic happens here.
+"""
+from __future__ import annotations
+
+from ._binding import Context
+
+INV_SQRT2 = 0.70710678118654752440
+
+# Black-Scholes (section 7): one index task per NumPy operation; sig, rv and r
+# are 0-d stores broadcast through the None partition.
+BS_STREAM = [
+    ("sqrt", ["T"], "sqrtT", ()), ("mul", ["sqrtT", "sig"], "vs", ()),
+    ("div", ["S", "K"], "SK", ()), ("log", ["SK"], "lnSK", ()),
+    ("mul", ["T", "rv"], "A", ()), ("add", ["lnSK", "A"], "B", ()),
+    ("div", ["B", "vs"], "d1", ()), ("sub", ["d1", "vs"], "d2", ()),
+    ("mul_imm", ["d1"], "e1", (INV_SQRT2,)), ("erf", ["e1"], "f1", ()),
+    ("add_imm", ["f1"], "g1", (1.0,)), ("mul_imm", ["g1"], "N1", (0.5,)),
+    ("mul_imm", ["d2"], "e2", (INV_SQRT2,)), ("erf", ["e2"], "f2", ()),
+    ("add_imm", ["f2"], "g2", (1.0,)), ("mul_imm", ["g2"], "N2", (0.5,)),
+    ("mul", ["T", "r"], "rT", ()), ("neg", ["rT"], "nrT", ()),
+    ("exp", ["nrT"], "disc", ()), ("mul", ["K", "disc"], "Kd", ()),
+    ("mul", ["S", "N1"], "SN1", ()), ("mul", ["Kd", "N2"], "KN2", ()),
+    ("sub", ["SN1", "KN2"], "call", ()), ("rsub_imm", ["N2"], "oN2", (1.0,)),
+    ("rsub_imm", ["N1"], "oN1", (1.0,)), ("mul", ["Kd", "oN2"], "KoN2", ()),
+    ("mul", ["S", "oN1"], "SoN1", ()), ("sub", ["KoN2", "SoN1"], "put", ()),
+]
+BS_SCALARS = ("sig", "rv", "r")
+
+
+def black_scholes(ctx: Context, S, K, T, r, sig, rv, n, dtype="f64", points=1):
+    """Submit one pricing pass; returns (call, put) store handles.
+
+    S, K, T are 1-D stores of n options, r/sig/rv 0-d stores; the launch
+    domain has `points` points, each pricing n/points options."""
+    assert n % points == 0
+    tile = ctx.part_tiling([n // points])
+    none = ctx.part_none()
+    names = {"S": S, "K": K, "T": T, "r": r, "sig": sig, "rv": rv}
+    made = []
+    for op, ins, out, imm in BS_STREAM:
+        o = ctx.store_create([n], dtype)
+        args = [(names[a], none if a in BS_SCALARS else tile, "R") for a in ins]
+        args.append((o, tile, "W"))
+        ctx.submit(op, [points], args, imm)
+        names[out] = o
+        made.append(out)
+    # leaving the pricing function drops every local but the results
+    for m in made:
+        if m not in ("call", "put"):
+            ctx.store_release(names[m])
+    return names["call"], names["put"]
+
+
+class Jacobi:
+    """5-point stencil sweeps over aliasing views of one grid (section 2)."""
+
+    def __init__(self, ctx: Context, grid: int, N: int, points=(1, 1)):
+        self.ctx, self.grid, self.N = ctx, grid, N
+        m = N - 2
+        assert m % points[0] == 0 and m % points[1] == 0
+        self.points = list(points)
+        tile = [m // points[0], m // points[1]]
+        self.m = m
+        self.view = {k: ctx.part_tiling(tile, off) for k, off in
+                     (("c", (1, 1)), ("n", (0, 1)), ("s", (2, 1)), ("w", (1, 0)), ("e", (1, 2)))}
+        self.T0 = ctx.part_tiling(tile, (0, 0))
+        self.none = ctx.part_none()
+        self.live = {}   # names the program currently binds
+
+    def _bind(self, name, store):
+        old = self.live.get(name)
+        self.live[name] = store
+        if old is not None:
+            self.ctx.store_release(old)
+
+    def sweep(self):
+        """avg = c + n + e + w + s; work = 0.2*avg; ss = sum((work-c)^2);
+        center[:] = work; res = sqrt(ss).  Returns the res store."""
+        c, G, V, T0, d = self.ctx, self.grid, self.view, self.T0, self.points
+        mk = lambda: c.store_create([self.m, self.m], "f64")
+        t1 = mk(); c.submit("add", d, [(G, V["c"], "R"), (G, V["n"], "R"), (t1, T0, "W")])
+        t2 = mk(); c.submit("add", d, [(t1, T0, "R"), (G, V["e"], "R"), (t2, T0, "W")])
+        c.store_release(t1)
+        t3 = mk(); c.submit("add", d, [(t2, T0, "R"), (G, V["w"], "R"), (t3, T0, "W")])
+        c.store_release(t2)
+        avg = mk(); c.submit("add", d, [(t3, T0, "R"), (G, V["s"], "R"), (avg, T0, "W")])
+        c.store_release(t3)
+        self._bind("avg", avg)
+        work = mk(); c.submit("mul_imm", d, [(avg, T0, "R"), (work, T0, "W")], (0.2,))
+        self._bind("work", work)
+        dd = mk(); c.submit("sub", d, [(work, T0, "R"), (G, V["c"], "R"), (dd, T0, "W")])
+        self._bind("d", dd)
+        ss = c.store_create([], "f64")
+        c.submit("sumsq", d, [(dd, T0, "R"), (ss, self.none, "Rd")], (1,))
+        self._bind("ss", ss)
+        c.submit("copy", d, [(work, T0, "R"), (G, V["c"], "W")])
+        res = c.store_create([], "f64")
+        c.submit("sqrt", [], [(ss, self.none, "R"), (res, self.none, "W")])
+        self._bind("res", res)
+        return res
+
+    def release_all(self):
+        for s in self.live.values():
+            self.ctx.store_release(s)
+        self.live.clear()
+
+
+class CG:
+    """Conjugate gradient (Hestenes-Stiefel) as issued by a SciPy-style
+    program: SpMV, dot products, scalar divides, axpys (section 7)."""
+
+    def __init__(self, ctx: Context, rowptr, col, val, b, n, points=1):
+        self.ctx, self.n = ctx, n
+        c = ctx
+        self.rowptr, self.col, self.val = rowptr, col, val
+        self.none = c.part_none()
+        self.tile = c.part_tiling([n // points])
+        self.img = c.part_image(col, self.none)
+        self.d = [points]
+        vec = lambda: c.store_create([n], "f64")
+        sc = lambda: c.store_create([], "f64")
+        self.x, self.r, self.p, self.q = vec(), vec(), vec(), vec()
+        self.pq, self.rho, self.rho_new, self.alpha, self.beta = sc(), sc(), sc(), sc(), sc()
+        T, N, d = self.tile, self.none, self.d
+        # x = 0; r = b; p = r; rho = r.r
+        c.submit("fill", d, [(self.x, T, "W")], (0.0,))
+        c.submit("copy", d, [(b, T, "R"), (self.r, T, "W")])
+        c.submit("copy", d, [(self.r, T, "R"), (self.p, T, "W")])
+        c.submit("dot", d, [(self.r, T, "R"), (self.r, T, "R"), (self.rho, N, "Rd")], (1,))
+
+    def iteration(self):
+        c, T, N, d = self.ctx, self.tile, self.none, self.d
+        x, r, p, q = self.x, self.r, self.p, self.q
+        c.submit("spmv_csr", d, [(self.rowptr, N, "R"), (self.col, N, "R"), (self.val, N, "R"),
+                                 (p, self.img, "R"), (q, T, "W")])
+        c.submit("dot", d, [(p, T, "R"), (q, T, "R"), (self.pq, N, "Rd")], (1,))
+        c.submit("div", [], [(self.rho, N, "R"), (self.pq, N, "R"), (self.alpha, N, "W")])
+        c.submit("axpy", d, [(self.alpha, N, "R"), (p, T, "R"), (x, T, "RW")], (1.0,))
+        c.submit("axpy", d, [(self.alpha, N, "R"), (q, T, "R"), (r, T, "RW")], (-1.0,))
+        c.submit("dot", d, [(r, T, "R"), (r, T, "R"), (self.rho_new, N, "Rd")], (1,))
+        c.submit("div", [], [(self.rho_new, N, "R"), (self.rho, N, "R"), (self.beta, N, "W")])
+        c.submit("copy", [], [(self.rho_new, N, "R"), (self.rho, N, "W")])
+        c.submit("mul", d, [(p, T, "R"), (self.beta, N, "R"), (p, T, "W")])
+        c.submit("add", d, [(p, T, "R"), (r, T, "R"), (p, T, "W")])

@@ -1,0 +1,1470 @@
+// Host core of the fused task-stream executor: the IR tables of section 3,
+// the task window and fusion analysis of section 4.2, temporary elimination
+// and memoisation (sections 5.1 and 5.2), lowering of a fused group to op
+// lists, and dispatch to the HIP kernels.
+#include "core.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+
+namespace dfx {
+
+// ---------------------------------------------------------------------------
+// Operation table: one entry per op (the per-op "generator" of section 6,
+// here a descriptor the lowering reads).
+static const OpInfo kOps[] = {
+    {DFX_OP_NEG, "neg", K_UNARY, 2, VO_NEG},
+    {DFX_OP_ABS, "abs", K_UNARY, 2, VO_ABS},
+    {DFX_OP_SQRT, "sqrt", K_UNARY, 2, VO_SQRT},
+    {DFX_OP_EXP, "exp", K_UNARY, 2, VO_EXP},
+    {DFX_OP_LOG, "log", K_UNARY, 2, VO_LOG},
+    {DFX_OP_ERF, "erf", K_UNARY, 2, VO_ERF},
+    {DFX_OP_SQUARE, "square", K_UNARY, 2, VO_SQUARE},
+    {DFX_OP_COPY, "copy", K_UNARY, 2, VO_MOV},
+    {DFX_OP_ADD, "add", K_BINARY, 3, VO_ADD},
+    {DFX_OP_SUB, "sub", K_BINARY, 3, VO_SUB},
+    {DFX_OP_MUL, "mul", K_BINARY, 3, VO_MUL},
+    {DFX_OP_DIV, "div", K_BINARY, 3, VO_DIV},
+    {DFX_OP_POW, "pow", K_BINARY, 3, VO_POW},
+    {DFX_OP_MAX, "max", K_BINARY, 3, VO_MAX},
+    {DFX_OP_MIN, "min", K_BINARY, 3, VO_MIN},
+    {DFX_OP_ADD_IMM, "add_imm", K_IMM, 2, VO_ADDI},
+    {DFX_OP_SUB_IMM, "sub_imm", K_IMM, 2, VO_SUBI},
+    {DFX_OP_RSUB_IMM, "rsub_imm", K_IMM, 2, VO_RSUBI},
+    {DFX_OP_MUL_IMM, "mul_imm", K_IMM, 2, VO_MULI},
+    {DFX_OP_DIV_IMM, "div_imm", K_IMM, 2, VO_DIVI},
+    {DFX_OP_RDIV_IMM, "rdiv_imm", K_IMM, 2, VO_RDIVI},
+    {DFX_OP_FILL, "fill", K_FILL, 1, VO_FILL},
+    {DFX_OP_AXPY, "axpy", K_AXPY, 3, VO_ADD},
+    {DFX_OP_SUM, "sum", K_RED, 2, VO_RED},
+    {DFX_OP_SUMSQ, "sumsq", K_RED, 2, VO_REDPROD},
+    {DFX_OP_DOT, "dot", K_RED, 3, VO_REDPROD},
+    {DFX_OP_SPMV_CSR, "spmv_csr", K_SPMV, 5, 0},
+};
+
+static const OpInfo* op_info(uint32_t op) {
+  for (const auto& o : kOps)
+    if (o.op == op) return &o;
+  return nullptr;
+}
+
+static bool is_float(int dt) { return dt == DFX_F32 || dt == DFX_F64; }
+static size_t dtype_size(int dt) { return (dt == DFX_F32 || dt == DFX_I32) ? 4 : 8; }
+static bool reads(int pr) { return pr == DFX_R || pr == DFX_RW; }
+static bool writes(int pr) { return pr == DFX_W || pr == DFX_RW; }
+static bool reduces(int pr) { return pr == DFX_RD; }
+static bool heavy_op(int vm) { return vm >= VO_FIRST_HEAVY; }
+
+static int fail(Ctx& c, int code, const std::string& msg) {
+  c.err = msg;
+  return code;
+}
+
+#define HIPCHK(c, expr)                                                             \
+  do {                                                                              \
+    hipError_t e__ = (expr);                                                        \
+    if (e__ != hipSuccess)                                                          \
+      return fail((c), DFX_EHIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory
+
+static void* dev_alloc(Ctx& c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (c.cfg.alloc) return c.cfg.alloc(bytes, (void*)c.stream, c.cfg.alloc_user);
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, c.stream) != hipSuccess) return nullptr;
+  return p;
+}
+
+static void dev_free(Ctx& c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c.cfg.dealloc) {
+    c.cfg.dealloc(p, bytes, (void*)c.stream, c.cfg.alloc_user);
+    return;
+  }
+  (void)hipFreeAsync(p, c.stream);
+}
+
+static int ensure_alloc(Ctx& c, StoreRec& s) {
+  if (s.ptr || s.bytes == 0) return DFX_OK;
+  if (c.analysis_only) return DFX_OK;
+  if (c.capturing)
+    return fail(c, DFX_ESTATE, "store " + std::to_string(s.id) +
+                                   " needs memory while a graph is being recorded");
+  s.ptr = dev_alloc(c, s.bytes);
+  if (!s.ptr) return fail(c, DFX_ENOMEM, "device allocation of " + std::to_string(s.bytes) + " bytes failed");
+  return DFX_OK;
+}
+
+static void maybe_free(Ctx& c, int64_t id) {
+  auto it = c.stores.find(id);
+  if (it == c.stores.end()) return;
+  StoreRec& s = it->second;
+  if (s.app_refs > 0 || s.pending > 0) return;
+  if (s.ptr && !s.external) dev_free(c, s.ptr, s.bytes);
+  c.stores.erase(it);
+}
+
+// ---------------------------------------------------------------------------
+// Interning of projections and partitions (structural equality = handle equality)
+
+// Interning keys list the fields explicitly (struct padding is not part of
+// a partition's structure).
+static void put_i64(std::string& k, int64_t v) { k.append((const char*)&v, 8); }
+
+static std::string proj_key(const ProjRec& r) {
+  std::string k;
+  put_i64(k, r.nin);
+  put_i64(k, r.nout);
+  for (int i = 0; i < r.nout; ++i) put_i64(k, r.keep[i]);
+  return k;
+}
+
+static std::string part_key(const PartRec& r) {
+  std::string k;
+  put_i64(k, r.kind);
+  put_i64(k, r.ndim);
+  for (int i = 0; i < r.ndim; ++i) { put_i64(k, r.tile[i]); put_i64(k, r.off[i]); }
+  put_i64(k, r.proj);
+  put_i64(k, r.img_src);
+  put_i64(k, r.img_part);
+  return k;
+}
+
+static int intern_proj(Ctx& c, const ProjRec& r) {
+  std::string k = proj_key(r);
+  auto it = c.proj_index.find(k);
+  if (it != c.proj_index.end()) return it->second;
+  int id = (int)c.projs.size();
+  c.projs.push_back(r);
+  c.proj_index.emplace(k, id);
+  return id;
+}
+
+static int intern_part(Ctx& c, const PartRec& r) {
+  std::string k = part_key(r);
+  auto it = c.part_index.find(k);
+  if (it != c.part_index.end()) return it->second;
+  int id = (int)c.parts.size();
+  c.parts.push_back(r);
+  c.part_index.emplace(k, id);
+  return id;
+}
+
+// ---------------------------------------------------------------------------
+// Validation of a submitted task
+
+static bool same_domain(const TaskRec& a, const TaskRec& b) {
+  if (a.ndim != b.ndim) return false;
+  for (int i = 0; i < a.ndim; ++i)
+    if (a.launch[i] != b.launch[i]) return false;
+  return true;
+}
+
+// Iteration space of a task: launch domain times the element shape of one
+// point (index task), or the shape of its array arguments (single task).
+struct Space {
+  int rank = 1;
+  int64_t d[DFX_MAX_DIM] = {1, 1, 1, 1};
+};
+
+static bool space_eq(const Space& a, const Space& b) {
+  if (a.rank != b.rank) return false;
+  for (int i = 0; i < a.rank; ++i)
+    if (a.d[i] != b.d[i]) return false;
+  return true;
+}
+
+struct TaskShape {
+  Space space;
+  int dtype = DFX_F64;
+  int64_t elem[DFX_MAX_DIM] = {1, 1, 1, 1};
+};
+
+static int task_shape(Ctx& c, const TaskRec& t, TaskShape& out) {
+  const OpInfo* oi = op_info(t.op);
+  int dt = -1;
+  for (size_t i = 0; i < t.args.size(); ++i) {
+    const StoreRec& s = c.stores.at(t.args[i].store);
+    if (oi->kind == K_SPMV && (i == 0 || i == 1)) continue;
+    if (dt < 0) dt = s.dtype;
+  }
+  out.dtype = dt < 0 ? DFX_F64 : dt;
+  if (oi->kind == K_SPMV) {
+    const PartRec& py = c.parts[t.args[4].part];
+    const StoreRec& y = c.stores.at(t.args[4].store);
+    out.space.rank = 1;
+    if (t.ndim == 0) out.space.d[0] = y.shape[0];
+    else out.space.d[0] = py.tile[0] * t.launch[0];
+    out.elem[0] = t.ndim == 0 ? y.shape[0] : py.tile[0];
+    return DFX_OK;
+  }
+  if (t.ndim == 0) {
+    // single task: array arguments through None, all of one shape
+    int rank = 0;
+    int64_t shp[DFX_MAX_DIM] = {1, 1, 1, 1};
+    for (const auto& a : t.args) {
+      const StoreRec& s = c.stores.at(a.store);
+      if (s.ndim == 0) continue;
+      if (rank == 0) {
+        rank = s.ndim;
+        for (int k = 0; k < rank; ++k) shp[k] = s.shape[k];
+      } else {
+        if (s.ndim != rank) return fail(c, DFX_EINVAL, "single task arrays differ in rank");
+        for (int k = 0; k < rank; ++k)
+          if (s.shape[k] != shp[k]) return fail(c, DFX_EINVAL, "single task arrays differ in shape");
+      }
+    }
+    if (rank == 0) {
+      out.space.rank = 1;
+      out.space.d[0] = 1;
+    } else {
+      out.space.rank = rank;
+      for (int k = 0; k < rank; ++k) out.space.d[k] = shp[k];
+    }
+    for (int k = 0; k < rank; ++k) out.elem[k] = shp[k];
+    return DFX_OK;
+  }
+  bool have = false;
+  for (const auto& a : t.args) {
+    const PartRec& p = c.parts[a.part];
+    if (p.kind != PK_TILING) continue;
+    const ProjRec& pj = c.projs[p.proj];
+    if (pj.nout == t.ndim) {
+      bool ident = true;
+      for (int k = 0; k < pj.nout; ++k) ident = ident && pj.keep[k] == k;
+      if (ident) {
+        for (int k = 0; k < t.ndim; ++k) out.elem[k] = p.tile[k];
+        have = true;
+        break;
+      }
+    }
+  }
+  if (!have) return fail(c, DFX_EINVAL, "index task needs an argument tiled with the identity projection");
+  out.space.rank = t.ndim;
+  for (int k = 0; k < t.ndim; ++k) out.space.d[k] = out.elem[k] * t.launch[k];
+  return DFX_OK;
+}
+
+static int validate(Ctx& c, const TaskRec& t) {
+  const OpInfo* oi = op_info(t.op);
+  if (!oi) return fail(c, DFX_EINVAL, "unknown op " + std::to_string(t.op));
+  if ((int)t.args.size() != oi->nargs)
+    return fail(c, DFX_EINVAL, std::string(oi->name) + " takes " + std::to_string(oi->nargs) + " arguments");
+  if (t.ndim < 0 || t.ndim > DFX_MAX_DIM) return fail(c, DFX_EINVAL, "launch rank out of range");
+  int64_t volume = 1;
+  for (int i = 0; i < t.ndim; ++i) {
+    if (t.launch[i] < 1) return fail(c, DFX_EINVAL, "launch extents must be >= 1");
+    volume *= t.launch[i];
+  }
+  for (const auto& a : t.args) {
+    if (!c.stores.count(a.store)) return fail(c, DFX_ENOTFOUND, "unknown store " + std::to_string(a.store));
+    if (a.part < 0 || a.part >= (int)c.parts.size()) return fail(c, DFX_ENOTFOUND, "unknown partition");
+    if (a.priv < DFX_R || a.priv > DFX_RD) return fail(c, DFX_EINVAL, "bad privilege");
+    if (c.stores.at(a.store).app_refs <= 0)
+      return fail(c, DFX_EINVAL, "store " + std::to_string(a.store) + " was released");
+  }
+  // privileges by role
+  auto need = [&](int i, bool in, bool out_, bool red) -> int {
+    int pr = t.args[i].priv;
+    if (red) return pr == DFX_RD ? DFX_OK : fail(c, DFX_EINVAL, std::string(oi->name) + ": result needs Rd");
+    if (in && !out_ && !reads(pr)) return fail(c, DFX_EINVAL, std::string(oi->name) + ": argument " + std::to_string(i) + " needs R");
+    if (out_ && !in && !writes(pr)) return fail(c, DFX_EINVAL, std::string(oi->name) + ": argument " + std::to_string(i) + " needs W");
+    if (out_ && in && pr != DFX_RW) return fail(c, DFX_EINVAL, std::string(oi->name) + ": argument " + std::to_string(i) + " needs RW");
+    return DFX_OK;
+  };
+  int rc = DFX_OK;
+  const int n = (int)t.args.size();
+  switch (oi->kind) {
+    case K_UNARY: case K_IMM: rc = need(0, true, false, false); if (!rc) rc = need(1, false, true, false); break;
+    case K_BINARY: rc = need(0, true, false, false); if (!rc) rc = need(1, true, false, false); if (!rc) rc = need(2, false, true, false); break;
+    case K_FILL: rc = need(0, false, true, false); break;
+    case K_AXPY: rc = need(0, true, false, false); if (!rc) rc = need(1, true, false, false); if (!rc) rc = need(2, true, true, false); break;
+    case K_RED: for (int i = 0; i < n - 1 && !rc; ++i) rc = need(i, true, false, false); if (!rc) rc = need(n - 1, false, false, true); break;
+    case K_SPMV: for (int i = 0; i < 4 && !rc; ++i) rc = need(i, true, false, false); if (!rc) rc = need(4, false, true, false); break;
+  }
+  if (rc) return rc;
+  if ((oi->kind == K_IMM || oi->kind == K_FILL) && t.imm.empty())
+    return fail(c, DFX_EINVAL, std::string(oi->name) + " needs an immediate");
+  // dtypes
+  int fdt = -1;
+  for (int i = 0; i < n; ++i) {
+    const StoreRec& s = c.stores.at(t.args[i].store);
+    if (oi->kind == K_SPMV && i < 2) {
+      if (s.dtype != DFX_I32) return fail(c, DFX_EINVAL, "spmv_csr: rowptr and col must be I32");
+      continue;
+    }
+    if (!is_float(s.dtype)) return fail(c, DFX_EINVAL, std::string(oi->name) + ": arguments must be F32 or F64");
+    if (fdt < 0) fdt = s.dtype;
+    else if (s.dtype != fdt) return fail(c, DFX_EINVAL, std::string(oi->name) + ": mixed floating dtypes");
+  }
+  // partitions: kinds, ranks, bounds, legality
+  for (int i = 0; i < n; ++i) {
+    const ArgRec& a = t.args[i];
+    const StoreRec& s = c.stores.at(a.store);
+    const PartRec& p = c.parts[a.part];
+    const bool spmv_mat = oi->kind == K_SPMV && i < 3;
+    const bool spmv_x = oi->kind == K_SPMV && i == 3;
+    if (p.kind == PK_IMAGE) {
+      if (!spmv_x) return fail(c, DFX_EINVAL, "Image partitions are only read as the gathered SpMV operand");
+      continue;
+    }
+    if (t.ndim == 0 && p.kind != PK_NONE) return fail(c, DFX_EINVAL, "single tasks take None partitions");
+    if (p.kind == PK_NONE) {
+      if (t.ndim > 0 && s.ndim == 0 && writes(a.priv))
+        return fail(c, DFX_EINVAL, "index tasks reduce into 0-d stores; single tasks write them");
+      if (writes(a.priv) && volume > 1)
+        return fail(c, DFX_EINVAL, "writing through None from several points interferes");
+      if (t.ndim > 0 && s.ndim != 0 && !spmv_mat && !spmv_x)
+        return fail(c, DFX_EINVAL, "None partitions of index tasks are for 0-d broadcasts");
+      if (reduces(a.priv) && s.ndim != 0) return fail(c, DFX_EINVAL, "reductions produce 0-d stores");
+      continue;
+    }
+    // Tiling
+    if (spmv_mat) return fail(c, DFX_EINVAL, "spmv_csr: matrix arrays are read through None");
+    if (reduces(a.priv)) return fail(c, DFX_EINVAL, "reductions produce 0-d stores through None");
+    if (p.ndim != s.ndim) return fail(c, DFX_EINVAL, "partition rank differs from store rank");
+    const ProjRec& pj = c.projs[p.proj];
+    if (pj.nin != t.ndim || pj.nout != s.ndim)
+      return fail(c, DFX_EINVAL, "projection ranks do not match launch and store");
+    for (int k = 0; k < s.ndim; ++k) {
+      const int64_t ext = p.tile[k] * t.launch[pj.keep[k]];
+      if (p.off[k] < 0 || p.off[k] + ext > s.shape[k])
+        return fail(c, DFX_EINVAL, "tiles of store " + std::to_string(s.id) + " leave its bounds");
+    }
+    if (writes(a.priv)) {
+      bool used[DFX_MAX_DIM] = {false, false, false, false};
+      for (int k = 0; k < pj.nout; ++k) used[pj.keep[k]] = true;
+      for (int d = 0; d < t.ndim; ++d)
+        if (!used[d] && t.launch[d] > 1)
+          return fail(c, DFX_EINVAL, "writing through an aliased (projected) tiling interferes");
+    }
+  }
+  // a point task may not write a store it also reads through another partition
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (i == j || t.args[i].store != t.args[j].store) continue;
+      if (writes(t.args[i].priv) && t.args[i].part != t.args[j].part)
+        return fail(c, DFX_EINVAL, "task writes store " + std::to_string(t.args[i].store) +
+                                       " and accesses it through another partition");
+      if (reduces(t.args[i].priv) && !reduces(t.args[j].priv))
+        return fail(c, DFX_EINVAL, "task reduces a store it also reads or writes");
+    }
+  TaskShape ts;
+  rc = task_shape(c, t, ts);
+  if (rc) return rc;
+  // element shapes of all tiled arguments agree
+  if (t.ndim > 0) {
+    for (int i = 0; i < n; ++i) {
+      const PartRec& p = c.parts[t.args[i].part];
+      if (p.kind != PK_TILING) continue;
+      const ProjRec& pj = c.projs[p.proj];
+      for (int k = 0; k < pj.nout; ++k)
+        if (p.tile[k] != ts.elem[pj.keep[k]])
+          return fail(c, DFX_EINVAL, "tiles of the arguments do not share one element shape");
+    }
+  }
+  if (oi->kind == K_SPMV) {
+    const StoreRec& rp = c.stores.at(t.args[0].store);
+    const StoreRec& col = c.stores.at(t.args[1].store);
+    const StoreRec& val = c.stores.at(t.args[2].store);
+    const StoreRec& y = c.stores.at(t.args[4].store);
+    const StoreRec& x = c.stores.at(t.args[3].store);
+    if (rp.ndim != 1 || col.ndim != 1 || val.ndim != 1 || x.ndim != 1 || y.ndim != 1)
+      return fail(c, DFX_EINVAL, "spmv_csr: all arrays are 1-D");
+    if (rp.shape[0] != y.shape[0] + 1) return fail(c, DFX_EINVAL, "spmv_csr: rowptr needs rows+1 entries");
+    if (col.shape[0] != val.shape[0]) return fail(c, DFX_EINVAL, "spmv_csr: col and val differ in length");
+    if (t.ndim > 1) return fail(c, DFX_EINVAL, "spmv_csr: 1-D launch domain");
+    const PartRec& py = c.parts[t.args[4].part];
+    if (t.ndim == 1 && py.kind != PK_TILING) return fail(c, DFX_EINVAL, "spmv_csr: y is tiled by rows");
+    if (t.ndim == 1 && py.off[0] != 0) return fail(c, DFX_EINVAL, "spmv_csr: y's tiling starts at row 0");
+  }
+  return DFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fusion analysis over the window (section 4.2)
+
+// Longest prefix satisfying launch-domain equivalence, true dependence, anti
+// dependence and reduction, by a forward pass that records, per store, the
+// partitions it has been read and written through and whether it has been
+// reduced.  Each new task is checked against the effects of all earlier
+// tasks of the prefix; the constraints quantify over pairs, so the set of
+// fusible prefixes is closed under taking prefixes and the first violation
+// ends the longest one.
+struct Effects {
+  std::vector<int> read_parts, write_parts;
+  bool reduced = false;
+};
+
+static int longest_prefix(Ctx& c) {
+  const auto& W = c.window;
+  if (W.empty()) return 0;
+  std::unordered_map<int64_t, Effects> eff;
+  int f = 0;
+  for (size_t j = 0; j < W.size(); ++j) {
+    const TaskRec& t = W[j];
+    bool ok = same_domain(t, W[0]);
+    for (const auto& a : t.args) {
+      if (!ok) break;
+      auto it = eff.find(a.store);
+      if (it == eff.end()) continue;
+      const Effects& e = it->second;
+      if (reads(a.priv) || writes(a.priv)) {
+        for (int p : e.write_parts) if (p != a.part) ok = false;   // true dependence
+        if (e.reduced) ok = false;                                 // reduction
+      }
+      if (writes(a.priv))
+        for (int p : e.read_parts) if (p != a.part) ok = false;    // anti dependence
+      if (reduces(a.priv) && (!e.read_parts.empty() || !e.write_parts.empty()))
+        ok = false;                                                // reduction
+    }
+    if (!ok) break;
+    for (const auto& a : t.args) {
+      Effects& e = eff[a.store];
+      if (reads(a.priv) && std::find(e.read_parts.begin(), e.read_parts.end(), a.part) == e.read_parts.end())
+        e.read_parts.push_back(a.part);
+      if (writes(a.priv) && std::find(e.write_parts.begin(), e.write_parts.end(), a.part) == e.write_parts.end())
+        e.write_parts.push_back(a.part);
+      if (reduces(a.priv)) e.reduced = true;
+    }
+    f = (int)j + 1;
+  }
+  return f;
+}
+
+// covers(S, P): the sub-stores of P over the launch domain hold all of S.
+static bool covers(Ctx& c, const StoreRec& s, int part, const TaskRec& t) {
+  const PartRec& p = c.parts[part];
+  if (p.kind == PK_NONE) return true;
+  if (p.kind != PK_TILING) return false;
+  const ProjRec& pj = c.projs[p.proj];
+  for (int k = 0; k < s.ndim; ++k) {
+    if (p.off[k] > 0) return false;
+    if (p.off[k] + p.tile[k] * t.launch[pj.keep[k]] < s.shape[k]) return false;
+  }
+  return true;
+}
+
+// Temporary stores of the fusion of window[0, f) (section 5.1):
+//  (1) every read through P in the prefix follows, in an earlier prefix
+//      task, a write through the same P that covers the store;
+//  (2) no task after the prefix reads or reduces it;
+//  (3) no application reference remains.
+static std::set<int64_t> temporaries(Ctx& c, int f) {
+  const auto& W = c.window;
+  std::map<int64_t, std::vector<int>> covered;  // store -> covering write partitions so far
+  std::set<int64_t> bad, seen;
+  std::vector<int64_t> order;
+  for (int j = 0; j < f; ++j) {
+    const TaskRec& t = W[j];
+    for (const auto& a : t.args) {
+      if (!seen.count(a.store)) { seen.insert(a.store); order.push_back(a.store); }
+      if (reads(a.priv)) {
+        const auto& cv = covered[a.store];
+        if (std::find(cv.begin(), cv.end(), a.part) == cv.end()) bad.insert(a.store);
+      }
+    }
+    for (const auto& a : t.args)
+      if (writes(a.priv) && covers(c, c.stores.at(a.store), a.part, t)) covered[a.store].push_back(a.part);
+  }
+  std::set<int64_t> later;
+  for (size_t k = f; k < W.size(); ++k)
+    for (const auto& a : W[k].args)
+      if (reads(a.priv) || reduces(a.priv)) later.insert(a.store);
+  std::set<int64_t> temps;
+  for (int64_t s : order) {
+    if (bad.count(s) || later.count(s)) continue;
+    const StoreRec& r = c.stores.at(s);
+    if (r.app_refs > 0 || r.external) continue;
+    temps.insert(s);
+  }
+  return temps;
+}
+
+// Canonical form of the window (section 5.2): stores renamed by order of
+// first appearance, so isomorphic windows share one key.  The key also holds
+// what the plan depends on: ops, launch domains, immediates, partitions,
+// privileges, and each store's rank, shape, dtype and live bit.
+static void put(std::string& k, const void* p, size_t n) { k.append((const char*)p, n); }
+
+static std::string canonical_key(Ctx& c, std::vector<int64_t>& order) {
+  std::unordered_map<int64_t, int> idx;
+  order.clear();
+  auto cid = [&](int64_t s) {
+    auto it = idx.find(s);
+    if (it != idx.end()) return it->second;
+    int i = (int)order.size();
+    idx.emplace(s, i);
+    order.push_back(s);
+    return i;
+  };
+  std::string k;
+  k.reserve(1024);
+  int32_t n = (int32_t)c.window.size();
+  put(k, &n, 4);
+  for (const auto& t : c.window) {
+    put(k, &t.op, 4);
+    put(k, &t.ndim, 4);
+    put(k, t.launch, 8 * t.ndim);
+    int32_t ni = (int32_t)t.imm.size(), na = (int32_t)t.args.size();
+    put(k, &ni, 4);
+    if (ni) put(k, t.imm.data(), 8 * ni);
+    put(k, &na, 4);
+    for (const auto& a : t.args) {
+      int32_t s = cid(a.store);
+      put(k, &s, 4);
+      const PartRec& p = c.parts[a.part];
+      if (p.kind == PK_IMAGE) {
+        int32_t tag = -2 - cid(p.img_src);
+        put(k, &tag, 4);
+        put(k, &p.img_part, 4);
+      } else {
+        put(k, &a.part, 4);
+      }
+      put(k, &a.priv, 4);
+    }
+  }
+  for (int64_t s : order) {
+    const StoreRec& r = c.stores.at(s);
+    put(k, &r.ndim, 4);
+    put(k, r.shape, 8 * r.ndim);
+    put(k, &r.dtype, 4);
+    int32_t live = (r.app_refs > 0 || r.external) ? 1 : 0;
+    put(k, &live, 4);
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// Lowering a fused group to passes and op lists
+
+struct Box { int64_t lo[2], hi[2]; };
+
+static int64_t union_volume(const std::vector<Box>& bs) {
+  if (bs.empty()) return 0;
+  std::vector<int64_t> xs, ys;
+  for (const auto& b : bs) { xs.push_back(b.lo[0]); xs.push_back(b.hi[0]); ys.push_back(b.lo[1]); ys.push_back(b.hi[1]); }
+  std::sort(xs.begin(), xs.end()); xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+  std::sort(ys.begin(), ys.end()); ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+  int64_t v = 0;
+  for (size_t i = 0; i + 1 < xs.size(); ++i)
+    for (size_t j = 0; j + 1 < ys.size(); ++j) {
+      bool in = false;
+      for (const auto& b : bs)
+        if (b.lo[0] <= xs[i] && xs[i + 1] <= b.hi[0] && b.lo[1] <= ys[j] && ys[j + 1] <= b.hi[1]) { in = true; break; }
+      if (in) v += (xs[i + 1] - xs[i]) * (ys[j + 1] - ys[j]);
+    }
+  return v;
+}
+
+struct SVal {
+  int kind;           // 0 input stream, 1 broadcast, 2 computed, 3 SpMV row result
+  int idx;            // stream / broadcast index, or defining instruction
+  int last_use = -1;
+  bool stored = false;
+  int reg = -1;
+  bool wb = false;
+};
+
+struct SInstr {
+  uint8_t op;
+  int a = -1, b = -1, dst = -1;   // value ids
+  int imm = 0, slot = 0;
+  bool dead = false;
+};
+
+struct Lowering {
+  Ctx& c;
+  const std::vector<int64_t>& order;  // canonical index -> store id
+  std::unordered_map<int64_t, int> cidx;
+  std::set<int64_t> temps;
+  Lowering(Ctx& c_, const std::vector<int64_t>& o) : c(c_), order(o) {
+    for (size_t i = 0; i < o.size(); ++i) cidx[o[i]] = (int)i;
+  }
+};
+
+// Stream (offset, row stride, column stride) of argument (s, part) in a pass
+// over `sp`; 1-D spaces are cut into rows of TW elements.
+static PStream make_stream(Ctx& c, const StoreRec& s, int part, const Space& sp, int tw, int cs) {
+  PStream ps{cs, 0, 0, 0};
+  int64_t st[DFX_MAX_DIM];
+  int64_t acc = 1;
+  for (int k = s.ndim - 1; k >= 0; --k) { st[k] = acc; acc *= s.shape[k]; }
+  const PartRec& p = c.parts[part];
+  if (s.ndim == 0) return ps;
+  int keep[DFX_MAX_DIM];
+  int64_t off[DFX_MAX_DIM] = {0, 0, 0, 0};
+  if (p.kind == PK_TILING) {
+    const ProjRec& pj = c.projs[p.proj];
+    for (int k = 0; k < s.ndim; ++k) { keep[k] = pj.keep[k]; off[k] = p.off[k]; }
+  } else {
+    for (int k = 0; k < s.ndim; ++k) keep[k] = k + (sp.rank - s.ndim);
+  }
+  int64_t srow = 0, scol = 0;
+  for (int k = 0; k < s.ndim; ++k) {
+    ps.off += off[k] * st[k];
+    if (sp.rank == 1) { if (keep[k] == 0) scol += st[k]; }
+    else {
+      if (keep[k] == 0) srow += st[k];
+      else if (keep[k] == 1) scol += st[k];
+    }
+  }
+  if (sp.rank == 1) { ps.s_row = scol * tw; ps.s_col = scol; }
+  else { ps.s_row = srow; ps.s_col = scol; }
+  return ps;
+}
+
+static Box stream_box(Ctx& c, const StoreRec& s, int part, const Space& sp) {
+  Box b{{0, 0}, {1, 1}};
+  const PartRec& p = c.parts[part];
+  if (s.ndim == 0) return b;
+  for (int k = 0; k < s.ndim && k < 2; ++k) {
+    int L;
+    int64_t off = 0;
+    if (p.kind == PK_TILING) { L = c.projs[p.proj].keep[k]; off = p.off[k]; }
+    else L = k + (sp.rank - s.ndim);
+    const int kk = s.ndim == 1 ? 1 : k;   // 1-D stores occupy the second box axis
+    b.lo[kk] = off;
+    b.hi[kk] = off + sp.d[L];
+  }
+  return b;
+}
+
+static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& tasks, const Space& sp,
+                      int dtype, int kind, PassPlan& out) {
+  const int tw = dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW;
+  const size_t es = dtype_size(dtype);
+  out.kind = kind;
+  out.dtype = dtype;
+  out.is1d = sp.rank == 1;
+  if (sp.rank == 1) {
+    out.n1d = sp.d[0];
+    out.rows = (sp.d[0] + tw - 1) / tw;
+    out.cols = tw;
+    out.strips = 1;
+  } else {
+    out.rows = sp.d[0];
+    out.cols = sp.d[1];
+    out.strips = (sp.d[1] + tw - 1) / tw;
+    out.n1d = sp.d[0] * sp.d[1];
+  }
+  const int64_t tile_rows = (out.rows + RED_TH - 1) / RED_TH;
+  out.n_tiles = tile_rows * out.strips;
+  if (out.n_tiles > (int64_t)FINAL_CHUNK * FINAL_CHUNK)
+    return fail(c, DFX_EUNSUPPORTED, "iteration space too large for the reduction tree");
+
+  std::vector<SVal> vals;
+  std::vector<SInstr> code;
+  std::map<std::pair<int, int>, int> cur;       // (cstore, part) -> value holding its current contents
+  std::map<std::pair<int, int>, int> in_index;  // (cstore, part) -> input stream index
+  std::map<int, int> bc_index;                  // cstore -> broadcast index
+  std::vector<std::pair<int, int>> written;     // (cstore, part) in first-write order
+  std::vector<std::pair<int64_t, int>> in_args; // (store id, part) per input stream
+
+  auto read_val = [&](const ArgRec& a) -> int {
+    const int cs = L.cidx.at(a.store);
+    auto key = std::make_pair(cs, a.part);
+    auto it = cur.find(key);
+    if (it != cur.end()) return it->second;
+    const StoreRec& s = c.stores.at(a.store);
+    if (kind != 2 && s.ndim == 0) {
+      auto bi = bc_index.find(cs);
+      if (bi != bc_index.end()) return bi->second;
+      int k = (int)out.bc_cstore.size();
+      out.bc_cstore.push_back(cs);
+      vals.push_back({1, k});
+      int v = (int)vals.size() - 1;
+      bc_index[cs] = v;
+      return v;
+    }
+    int k = (int)out.ins.size();
+    out.ins.push_back(make_stream(c, s, a.part, sp, tw, cs));
+    in_args.push_back({a.store, a.part});
+    vals.push_back({0, k});
+    int v = (int)vals.size() - 1;
+    in_index[key] = k;
+    cur[key] = v;
+    return v;
+  };
+  auto write_val = [&](const ArgRec& a, int v) {
+    const int cs = L.cidx.at(a.store);
+    auto key = std::make_pair(cs, a.part);
+    if (std::find(written.begin(), written.end(), key) == written.end()) written.push_back(key);
+    cur[key] = v;
+  };
+  auto emit = [&](uint8_t op, int a, int b, int imm, int slot, bool has_dst) -> int {
+    SInstr I;
+    I.op = op; I.a = a; I.b = b; I.imm = imm; I.slot = slot;
+    if (has_dst) {
+      vals.push_back({2, (int)code.size()});
+      I.dst = (int)vals.size() - 1;
+    }
+    code.push_back(I);
+    return I.dst;
+  };
+  auto add_imm = [&](double v) -> int {
+    for (size_t i = 0; i < out.imm.size(); ++i)
+      if (std::memcmp(&out.imm[i], &v, 8) == 0) return (int)i;
+    out.imm.push_back(v);
+    return (int)out.imm.size() - 1;
+  };
+
+  for (const TaskRec* t : tasks) {
+    const OpInfo* oi = op_info(t->op);
+    const auto& A = t->args;
+    switch (oi->kind) {
+      case K_UNARY: {
+        int x = read_val(A[0]);
+        int z = oi->vm == VO_MOV ? x : emit((uint8_t)oi->vm, x, x, 0, 0, true);
+        write_val(A[1], z);
+      } break;
+      case K_BINARY: {
+        int x = read_val(A[0]), y = read_val(A[1]);
+        write_val(A[2], emit((uint8_t)oi->vm, x, y, 0, 0, true));
+      } break;
+      case K_IMM: {
+        int x = read_val(A[0]);
+        write_val(A[1], emit((uint8_t)oi->vm, x, x, add_imm(t->imm[0]), 0, true));
+      } break;
+      case K_FILL: {
+        write_val(A[0], emit(VO_FILL, -1, -1, add_imm(t->imm[0]), 0, true));
+      } break;
+      case K_AXPY: {
+        int al = read_val(A[0]), x = read_val(A[1]), y = read_val(A[2]);
+        int p = emit(VO_MUL, al, x, 0, 0, true);
+        const bool minus = !t->imm.empty() && t->imm[0] < 0;
+        write_val(A[2], emit(minus ? VO_SUB : VO_ADD, y, p, 0, 0, true));
+      } break;
+      case K_RED: {
+        const int slot = (int)out.red_cstore.size();
+        if (slot >= VM_MAXRED) return fail(c, DFX_EUNSUPPORTED, "too many reductions in one pass");
+        const int cs = L.cidx.at(A.back().store);
+        out.red_cstore.push_back(cs);
+        out.red_init.push_back(!t->imm.empty() && t->imm[0] != 0);
+        int x = read_val(A[0]);
+        int y = t->op == DFX_OP_DOT ? read_val(A[1]) : x;
+        emit((uint8_t)oi->vm, x, y, 0, slot, false);
+      } break;
+      case K_SPMV: {
+        out.spmv_rowptr = L.cidx.at(A[0].store);
+        out.spmv_col = L.cidx.at(A[1].store);
+        out.spmv_val = L.cidx.at(A[2].store);
+        out.spmv_x = L.cidx.at(A[3].store);
+        vals.push_back({3, 0});
+        write_val(A[4], (int)vals.size() - 1);
+      } break;
+    }
+  }
+  // outputs: final value of every written, non-temporary (store, partition)
+  std::vector<std::pair<int, int>> outs;  // (value, written index)
+  for (size_t i = 0; i < written.size(); ++i) {
+    const int64_t sid = L.order[written[i].first];
+    if (L.temps.count(sid)) continue;
+    outs.push_back({cur[written[i]], (int)i});
+    vals[cur[written[i]]].stored = true;
+  }
+  // dead code: keep instructions whose values reach a store or a reduction
+  std::vector<bool> live(vals.size(), false);
+  for (auto& o : outs) live[o.first] = true;
+  for (int i = (int)code.size() - 1; i >= 0; --i) {
+    SInstr& I = code[i];
+    bool need = (I.op == VO_RED || I.op == VO_REDPROD) || (I.dst >= 0 && live[I.dst]);
+    if (!need) { I.dead = true; continue; }
+    if (I.a >= 0) live[I.a] = true;
+    if (I.b >= 0) live[I.b] = true;
+  }
+  std::vector<SInstr> kept;
+  for (auto& I : code)
+    if (!I.dead) kept.push_back(I);
+  code.swap(kept);
+  for (size_t i = 0; i < code.size(); ++i)
+    if (code[i].dst >= 0) vals[code[i].dst].idx = (int)i;
+  // operand uses
+  const int INF = 1 << 30;
+  std::vector<std::vector<int>> uses(vals.size());
+  for (size_t i = 0; i < code.size(); ++i) {
+    if (code[i].a >= 0) uses[code[i].a].push_back((int)i);
+    if (code[i].b >= 0 && code[i].b != code[i].a) uses[code[i].b].push_back((int)i);
+  }
+  for (size_t v = 0; v < vals.size(); ++v) {
+    int lu = -1;
+    for (int u : uses[v]) lu = std::max(lu, u);
+    if (vals[v].stored) lu = INF;
+    vals[v].last_use = lu;
+    if (vals[v].kind == 2) {
+      const int d = vals[v].idx;
+      bool only_next = !vals[v].stored && !uses[v].empty();
+      for (int u : uses[v]) only_next = only_next && u == d + 1;
+      vals[v].wb = !only_next;
+    }
+  }
+  // unused inputs are still loaded (their stream is bound); unused
+  // broadcasts are dropped from the register file but keep their slot
+  if (out.ins.size() > (size_t)VM_MAXIN || out.bc_cstore.size() > (size_t)VM_MAXBC ||
+      code.size() > (size_t)VM_MAXCODE || out.imm.size() > (size_t)VM_MAXIMM ||
+      outs.size() > (size_t)VM_MAXOUT)
+    return fail(c, DFX_EUNSUPPORTED, "fused pass exceeds the kernel's stream/op limits");
+
+  bool heavy = false;
+  for (auto& I : code) heavy = heavy || heavy_op(I.op);
+  // register allocation: inputs fixed at 0..n_in-1, SpMV result at NR-1,
+  // broadcasts in permanent registers above the inputs, computed values by
+  // linear scan (an operand's register is free for the instruction's result)
+  auto allocate = [&](int NR) -> bool {
+    for (auto& v : vals) v.reg = -1;
+    std::vector<int> busy_until(NR, -2);  // last instruction reading the register; INF permanent
+    const int nin = (int)out.ins.size();
+    if (nin > NR) return false;
+    const bool has_spmv = kind == 1;
+    for (size_t v = 0; v < vals.size(); ++v) {
+      if (vals[v].kind == 0) {
+        vals[v].reg = vals[v].idx;
+        busy_until[vals[v].idx] = std::max(vals[v].last_use, -1);
+      } else if (vals[v].kind == 3) {
+        if (NR - 1 < nin) return false;
+        vals[v].reg = NR - 1;
+        busy_until[NR - 1] = std::max(vals[v].last_use, -1);
+      }
+    }
+    if (has_spmv && busy_until[NR - 1] < -1) busy_until[NR - 1] = -1;
+    for (size_t v = 0; v < vals.size(); ++v) {
+      if (vals[v].kind != 1) continue;
+      int r = -1;
+      for (int q = nin; q < NR - (has_spmv ? 1 : 0); ++q)
+        if (busy_until[q] == -2) { r = q; break; }
+      if (r < 0) return false;
+      vals[v].reg = r;
+      busy_until[r] = INF;
+    }
+    for (size_t i = 0; i < code.size(); ++i) {
+      const int d = code[i].dst;
+      if (d < 0 || !vals[d].wb) continue;
+      int r = -1;
+      for (int q = 0; q < NR; ++q)
+        if (busy_until[q] != INF && busy_until[q] <= (int)i) { r = q; break; }
+      if (r < 0) return false;
+      vals[d].reg = r;
+      busy_until[r] = vals[d].last_use;
+    }
+    return true;
+  };
+  int NR = VM_NREG_LIGHT;
+  if (heavy || out.ins.size() > 6 || !allocate(NR)) {
+    heavy = true;
+    NR = VM_NREG;
+    if (!allocate(NR)) return fail(c, DFX_EUNSUPPORTED, "fused pass needs more than 16 live values");
+  }
+  out.heavy = heavy;
+  // emit kernel instructions with operand forwarding
+  out.code.clear();
+  for (size_t i = 0; i < code.size(); ++i) {
+    const SInstr& I = code[i];
+    VmInstr K{};
+    K.op = I.op;
+    K.imm = (uint16_t)I.imm;
+    K.slot = (uint8_t)I.slot;
+    const int prev = i > 0 ? code[i - 1].dst : -1;
+    if (I.a >= 0) {
+      if (I.a == prev) K.flags |= VF_A_ACC;
+      else K.a = (uint8_t)vals[I.a].reg;
+    }
+    if (I.b >= 0) {
+      if (I.b == prev) K.flags |= VF_B_ACC;
+      else K.b = (uint8_t)vals[I.b].reg;
+    }
+    if (I.dst >= 0 && vals[I.dst].wb) {
+      K.flags |= VF_WB;
+      K.dst = (uint8_t)vals[I.dst].reg;
+    }
+    out.code.push_back(K);
+  }
+  for (auto& o : outs) {
+    const auto key = written[o.second];
+    const StoreRec& s = c.stores.at(L.order[key.first]);
+    out.outs.push_back(make_stream(c, s, key.second, sp, tw, key.first));
+    out.out_reg.push_back((uint8_t)vals[o.first].reg);
+  }
+  for (size_t v = 0; v < vals.size(); ++v)
+    if (vals[v].kind == 1) out.bc_reg.push_back((uint8_t)vals[v].reg);
+  out.unit_cols = 1;
+  for (auto& s : out.ins) out.unit_cols &= s.s_col == 1;
+  for (auto& s : out.outs) out.unit_cols &= s.s_col == 1;
+  // launch shape: contiguous tile chunks per wave
+  const int64_t target_waves = 8192;
+  out.tiles_per_wave = std::max<int64_t>(1, (out.n_tiles + target_waves - 1) / target_waves);
+  const int64_t waves = (out.n_tiles + out.tiles_per_wave - 1) / out.tiles_per_wave;
+  int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
+  if (grid > 8) grid = (grid + 7) / 8 * 8;
+  out.grid = (int)grid;
+  // algorithmic bytes: union footprint of every store read, and of every
+  // store written, once per pass
+  std::map<int64_t, std::vector<Box>> rd, wr;
+  for (auto& ia : in_args) rd[ia.first].push_back(stream_box(c, c.stores.at(ia.first), ia.second, sp));
+  for (auto& o : outs) {
+    const auto key = written[o.second];
+    const int64_t sid = L.order[key.first];
+    wr[sid].push_back(stream_box(c, c.stores.at(sid), key.second, sp));
+  }
+  int64_t bytes = 0;
+  for (auto& kv : rd) bytes += union_volume(kv.second) * (int64_t)es;
+  for (auto& kv : wr) bytes += union_volume(kv.second) * (int64_t)es;
+  bytes += (int64_t)(out.bc_cstore.size() + 2 * out.red_cstore.size()) * (int64_t)es;
+  if (kind == 1) {
+    const StoreRec& rp = c.stores.at(L.order[out.spmv_rowptr]);
+    const StoreRec& col = c.stores.at(L.order[out.spmv_col]);
+    const StoreRec& x = c.stores.at(L.order[out.spmv_x]);
+    bytes += rp.elems * 4 + col.elems * (4 + (int64_t)es) + x.elems * (int64_t)es;
+  }
+  out.alg_bytes = bytes;
+  return DFX_OK;
+}
+
+// Split the prefix into passes: maximal runs of tasks sharing one iteration
+// space and dtype; an SpMV starts a pass of its own kind.
+static int build_plan(Ctx& c, int f, const std::set<int64_t>& temps, const std::vector<int64_t>& order,
+                      Plan& plan) {
+  plan.prefix = f;
+  struct G { std::vector<const TaskRec*> tasks; Space sp; int dtype; int kind; };
+  std::vector<G> groups;
+  for (int j = 0; j < f; ++j) {
+    const TaskRec& t = c.window[j];
+    TaskShape ts;
+    int rc = task_shape(c, t, ts);
+    if (rc) return rc;
+    if (ts.space.rank > 2) return fail(c, DFX_EUNSUPPORTED, "iteration spaces of rank > 2 are not executable");
+    const bool sp = t.op == DFX_OP_SPMV_CSR;
+    const int kind = sp ? 1 : (t.ndim == 0 ? 2 : 0);
+    bool fresh = groups.empty() || sp || !space_eq(groups.back().sp, ts.space) ||
+                 groups.back().dtype != ts.dtype || (groups.back().kind == 2) != (kind == 2);
+    if (!fresh && groups.back().tasks.size() >= 48) fresh = true;
+    if (fresh) groups.push_back({{}, ts.space, ts.dtype, kind});
+    groups.back().tasks.push_back(&t);
+  }
+  // a temporary used by two passes must be materialised between them
+  std::map<int64_t, std::set<int>> used_in;
+  for (size_t g = 0; g < groups.size(); ++g)
+    for (auto* t : groups[g].tasks)
+      for (auto& a : t->args) used_in[a.store].insert((int)g);
+  Lowering L(c, order);
+  for (int64_t s : temps)
+    if (used_in[s].size() <= 1) L.temps.insert(s);
+  for (int64_t s : L.temps) plan.temps.push_back(L.cidx.at(s));
+  for (auto& g : groups) {
+    PassPlan pp;
+    int rc = lower_pass(c, L, g.tasks, g.sp, g.dtype, g.kind, pp);
+    if (rc) return rc;
+    plan.alg_bytes += pp.alg_bytes;
+    plan.passes.push_back(std::move(pp));
+  }
+  return DFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Execution
+
+static void* g_dummy_stream = nullptr;  // zeroed 4 KB read by padding stream slots
+
+static int ensure_workspace(Ctx& c, PassPlan& p) {
+  if (c.analysis_only || p.red_cstore.empty() || p.ws) return DFX_OK;
+  if (c.capturing) return fail(c, DFX_ESTATE, "a new fused window appeared while a graph is being recorded");
+  const size_t es = dtype_size(p.dtype);
+  const size_t part = (size_t)std::max<int64_t>(1, p.n_tiles) * es;
+  p.ws_bytes = part * p.red_cstore.size() + 256;
+  p.ws = dev_alloc(c, p.ws_bytes);
+  if (!p.ws) return fail(c, DFX_ENOMEM, "workspace allocation failed");
+  HIPCHK(c, hipMemsetAsync(p.ws, 0, p.ws_bytes, c.stream));
+  return DFX_OK;
+}
+
+static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
+  auto S = [&](int cs) -> StoreRec& { return c.stores.at(order[cs]); };
+  const size_t es = dtype_size(p.dtype);
+  int rc;
+  for (auto& s : p.ins) if ((rc = ensure_alloc(c, S(s.cstore)))) return rc;
+  for (auto& s : p.outs) if ((rc = ensure_alloc(c, S(s.cstore)))) return rc;
+  for (int cs : p.bc_cstore) if ((rc = ensure_alloc(c, S(cs)))) return rc;
+  for (int cs : p.red_cstore) if ((rc = ensure_alloc(c, S(cs)))) return rc;
+  if (p.kind == 1)
+    for (int cs : {p.spmv_rowptr, p.spmv_col, p.spmv_val, p.spmv_x})
+      if ((rc = ensure_alloc(c, S(cs)))) return rc;
+  if ((rc = ensure_workspace(c, p))) return rc;
+  c.stats.launches += 1;
+  c.stats.alg_bytes += p.alg_bytes;
+  if (c.capturing) { c.capture_launches += 1; c.capture_bytes += p.alg_bytes; }
+  if (c.analysis_only) return DFX_OK;
+
+  VmParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.n_code = (int)p.code.size();
+  P.n_in = (int)p.ins.size();
+  P.n_out = (int)p.outs.size();
+  P.n_bc = (int)p.bc_cstore.size();
+  P.n_red = (int)p.red_cstore.size();
+  P.is1d = p.is1d;
+  P.spmv = p.kind == 1;
+  P.grid = p.grid;
+  P.unit_cols = p.unit_cols;
+  P.rows = p.rows;
+  P.cols = p.cols;
+  P.n1d = p.n1d;
+  P.n_tiles = p.n_tiles;
+  P.strips = p.strips;
+  P.tiles_per_wave = p.tiles_per_wave;
+  const int nb = stream_bucket(P.n_in);
+  for (int k = 0; k < VM_MAXIN; ++k) {
+    if (k < P.n_in) {
+      const PStream& s = p.ins[k];
+      P.in[k].base = (const char*)S(s.cstore).ptr + s.off * (int64_t)es;
+      P.in[k].s_row = s.s_row;
+      P.in[k].s_col = s.s_col;
+    } else if (k < nb) {
+      P.in[k].base = g_dummy_stream;
+      P.in[k].s_row = 0;
+      P.in[k].s_col = 0;
+    }
+  }
+  for (int k = 0; k < P.n_out; ++k) {
+    const PStream& s = p.outs[k];
+    P.out[k].base = (char*)S(s.cstore).ptr + s.off * (int64_t)es;
+    P.out[k].s_row = s.s_row;
+    P.out[k].s_col = s.s_col;
+    P.out_reg[k] = p.out_reg[k];
+  }
+  for (int k = 0; k < P.n_bc; ++k) {
+    P.bc[k] = S(p.bc_cstore[k]).ptr;
+    P.bc_reg[k] = p.bc_reg[k];
+  }
+  const size_t part = (size_t)std::max<int64_t>(1, p.n_tiles) * es;
+  for (int k = 0; k < P.n_red; ++k) {
+    P.red_partials[k] = (char*)p.ws + part * k;
+    P.red_result[k] = S(p.red_cstore[k]).ptr;
+    P.red_init[k] = p.red_init[k];
+  }
+  if (P.n_red) P.counter = (unsigned int*)((char*)p.ws + part * P.n_red);
+  if (p.kind == 1) {
+    P.rowptr = (const int32_t*)S(p.spmv_rowptr).ptr;
+    P.colidx = (const int32_t*)S(p.spmv_col).ptr;
+    P.val = S(p.spmv_val).ptr;
+    P.x = S(p.spmv_x).ptr;
+  }
+  for (size_t i = 0; i < p.imm.size(); ++i) P.imm[i] = p.imm[i];
+  for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
+  int e = launch_vm(P, p.dtype == DFX_F64, p.heavy, c.stream);
+  if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
+  return DFX_OK;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static int dispatch_one(Ctx& c) {
+  if (c.window.empty()) return DFX_OK;
+  std::vector<int64_t> order;
+  std::string key = canonical_key(c, order);
+  Plan* plan = nullptr;
+  std::unique_ptr<Plan> owned;
+  bool hit = false;
+  if (c.cfg.memo) {
+    auto it = c.memo.find(key);
+    if (it != c.memo.end()) { plan = it->second.get(); hit = true; }
+  }
+  if (!plan) {
+    const double t0 = now_s();
+    const int f = c.cfg.fuse ? longest_prefix(c) : 1;
+    std::set<int64_t> temps;
+    if (c.cfg.fuse) temps = temporaries(c, f);
+    owned.reset(new Plan());
+    int rc = build_plan(c, f, temps, order, *owned);
+    if (rc) {
+      if (!(c.analysis_only && rc == DFX_EUNSUPPORTED)) return rc;
+      owned->passes.clear();
+    }
+    c.stats.analysis_seconds += now_s() - t0;
+    c.stats.memo_misses += 1;
+    plan = owned.get();
+    if (c.cfg.memo) {
+      if (c.memo.size() >= 4096) c.memo.clear();
+      c.memo.emplace(key, std::move(owned));
+    }
+  } else {
+    c.stats.memo_hits += 1;
+  }
+  for (auto& p : plan->passes) {
+    int rc = run_pass(c, p, order);
+    if (rc) return rc;
+  }
+  // record the group
+  dfx_group_info gi;
+  std::memset(&gi, 0, sizeof(gi));
+  gi.first_task = c.window.front().seq;
+  gi.prefix_len = plan->prefix;
+  gi.memo_hit = hit;
+  gi.n_passes = (int)plan->passes.size();
+  for (int i = 0; i < gi.n_passes && i < 8; ++i) gi.pass_kind[i] = plan->passes[i].kind;
+  gi.n_temporaries = (int)std::min<size_t>(plan->temps.size(), DFX_INFO_MAX);
+  for (int i = 0; i < gi.n_temporaries; ++i) gi.temporaries[i] = order[plan->temps[i]];
+  gi.alg_bytes = plan->alg_bytes;
+  if (c.groups.size() < 1000000) c.groups.push_back(gi);
+  c.stats.groups_dispatched += 1;
+  c.stats.tasks_dispatched += plan->prefix;
+  c.stats.temporaries_eliminated += (int64_t)plan->temps.size();
+  // retire the prefix: drop the window's references
+  std::vector<int64_t> touched;
+  for (int j = 0; j < plan->prefix; ++j) {
+    const TaskRec& t = c.window.front();
+    std::set<int64_t> seen;
+    for (auto& a : t.args)
+      if (seen.insert(a.store).second) {
+        c.stores.at(a.store).pending -= 1;
+        touched.push_back(a.store);
+      }
+    c.window.pop_front();
+  }
+  for (int64_t s : touched) maybe_free(c, s);
+  return DFX_OK;
+}
+
+static int flush(Ctx& c) {
+  while (!c.window.empty()) {
+    int rc = dispatch_one(c);
+    if (rc) return rc;
+  }
+  return DFX_OK;
+}
+
+}  // namespace dfx
+
+// ===========================================================================
+// C ABI
+using namespace dfx;
+
+struct dfx_ctx : public dfx::Ctx {};
+
+extern "C" {
+
+const char* dfx_version(void) { return "dfx 0.1 (gfx950)"; }
+
+const char* dfx_last_error(dfx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dfx_create(const dfx_config* cfg, dfx_ctx** out) {
+  if (!cfg || !out) return DFX_EINVAL;
+  if (cfg->window_size < 1) return DFX_EINVAL;
+  dfx_ctx* c = new dfx_ctx();
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)cfg->stream;
+  c->analysis_only = cfg->device < 0;
+  if (!c->analysis_only) {
+    if (hipSetDevice(cfg->device) != hipSuccess) { delete c; return DFX_EHIP; }
+    if (!g_dummy_stream) {
+      if (hipMalloc(&g_dummy_stream, 4096) != hipSuccess) { delete c; return DFX_ENOMEM; }
+      if (hipMemset(g_dummy_stream, 0, 4096) != hipSuccess) { delete c; return DFX_EHIP; }
+    }
+    if (!cfg->alloc) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    }
+  }
+  *out = c;
+  return DFX_OK;
+}
+
+int dfx_destroy(dfx_ctx* c) {
+  if (!c) return DFX_EINVAL;
+  int rc = c->capturing ? DFX_OK : flush(*c);
+  if (!c->analysis_only) {
+    for (auto& kv : c->memo)
+      for (auto& p : kv.second->passes)
+        if (p.ws) dev_free(*c, p.ws, p.ws_bytes);
+    for (auto& kv : c->stores)
+      if (kv.second.ptr && !kv.second.external) dev_free(*c, kv.second.ptr, kv.second.bytes);
+    for (auto& g : c->graphs) {
+      if (g && g->exec) (void)hipGraphExecDestroy(g->exec);
+      if (g && g->graph) (void)hipGraphDestroy(g->graph);
+    }
+    (void)hipStreamSynchronize(c->stream);
+  }
+  delete c;
+  return rc;
+}
+
+static int new_store(dfx_ctx* c, int32_t ndim, const int64_t* shape, int32_t dtype, dfx_store* out,
+                     StoreRec** rec) {
+  if (!c || !out || ndim < 0 || ndim > DFX_MAX_DIM || (ndim > 0 && !shape))
+    return c ? fail(*c, DFX_EINVAL, "bad store arguments") : DFX_EINVAL;
+  if (dtype < DFX_F32 || dtype > DFX_I64) return fail(*c, DFX_EINVAL, "bad dtype");
+  StoreRec s;
+  s.id = c->next_store++;
+  s.ndim = ndim;
+  s.dtype = dtype;
+  s.elems = 1;
+  for (int k = 0; k < ndim; ++k) {
+    if (shape[k] < 0) return fail(*c, DFX_EINVAL, "negative extent");
+    s.shape[k] = shape[k];
+    s.elems *= shape[k];
+  }
+  s.bytes = (size_t)s.elems * dtype_size(dtype);
+  auto it = c->stores.emplace(s.id, s).first;
+  *out = s.id;
+  *rec = &it->second;
+  return DFX_OK;
+}
+
+int dfx_store_create(dfx_ctx* c, int32_t ndim, const int64_t* shape, int32_t dtype, dfx_store* out) {
+  StoreRec* r;
+  return new_store(c, ndim, shape, dtype, out, &r);
+}
+
+int dfx_store_wrap(dfx_ctx* c, void* dptr, int32_t ndim, const int64_t* shape, int32_t dtype,
+                   dfx_store* out) {
+  StoreRec* r;
+  int rc = new_store(c, ndim, shape, dtype, out, &r);
+  if (rc) return rc;
+  r->ptr = dptr;
+  r->external = true;
+  return DFX_OK;
+}
+
+static StoreRec* find_store(dfx_ctx* c, dfx_store s) {
+  auto it = c->stores.find(s);
+  return it == c->stores.end() ? nullptr : &it->second;
+}
+
+int dfx_store_write(dfx_ctx* c, dfx_store s, const void* host, size_t bytes) {
+  if (!c) return DFX_EINVAL;
+  int rc = flush(*c);
+  if (rc) return rc;
+  StoreRec* r = find_store(c, s);
+  if (!r) return fail(*c, DFX_ENOTFOUND, "unknown store");
+  if (bytes != r->bytes) return fail(*c, DFX_EINVAL, "byte count differs from the store's size");
+  if (c->analysis_only) return fail(*c, DFX_ESTATE, "analysis-only context holds no values");
+  if ((rc = ensure_alloc(*c, *r))) return rc;
+  if (bytes == 0) return DFX_OK;
+  HIPCHK(*c, hipMemcpyAsync(r->ptr, host, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(*c, hipStreamSynchronize(c->stream));
+  return DFX_OK;
+}
+
+int dfx_store_read(dfx_ctx* c, dfx_store s, void* host, size_t bytes) {
+  if (!c) return DFX_EINVAL;
+  int rc = flush(*c);
+  if (rc) return rc;
+  StoreRec* r = find_store(c, s);
+  if (!r) return fail(*c, DFX_ENOTFOUND, "unknown store");
+  if (bytes != r->bytes) return fail(*c, DFX_EINVAL, "byte count differs from the store's size");
+  if (c->analysis_only) return fail(*c, DFX_ESTATE, "analysis-only context holds no values");
+  if (bytes == 0) return DFX_OK;
+  if (!r->ptr) return fail(*c, DFX_ESTATE, "store was never written");
+  HIPCHK(*c, hipMemcpyAsync(host, r->ptr, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(*c, hipStreamSynchronize(c->stream));
+  return DFX_OK;
+}
+
+int dfx_store_device_ptr(dfx_ctx* c, dfx_store s, void** dptr) {
+  if (!c || !dptr) return DFX_EINVAL;
+  int rc = flush(*c);
+  if (rc) return rc;
+  StoreRec* r = find_store(c, s);
+  if (!r) return fail(*c, DFX_ENOTFOUND, "unknown store");
+  if (c->analysis_only) return fail(*c, DFX_ESTATE, "analysis-only context holds no values");
+  if ((rc = ensure_alloc(*c, *r))) return rc;
+  *dptr = r->ptr;
+  return DFX_OK;
+}
+
+int dfx_store_release(dfx_ctx* c, dfx_store s) {
+  if (!c) return DFX_EINVAL;
+  StoreRec* r = find_store(c, s);
+  if (!r || r->app_refs <= 0) return fail(*c, DFX_ENOTFOUND, "unknown or released store");
+  r->app_refs -= 1;
+  maybe_free(*c, s);
+  return DFX_OK;
+}
+
+int dfx_proj_identity(dfx_ctx* c, int32_t ndim, dfx_proj* out) {
+  if (!c || !out || ndim < 0 || ndim > DFX_MAX_DIM) return DFX_EINVAL;
+  ProjRec p;
+  p.nin = p.nout = ndim;
+  for (int k = 0; k < ndim; ++k) p.keep[k] = k;
+  *out = intern_proj(*c, p);
+  return DFX_OK;
+}
+
+int dfx_proj_drop(dfx_ctx* c, int32_t ndim_in, uint32_t keep_mask, dfx_proj* out) {
+  if (!c || !out || ndim_in < 0 || ndim_in > DFX_MAX_DIM) return DFX_EINVAL;
+  if (keep_mask >> ndim_in) return fail(*c, DFX_EINVAL, "keep mask names dims beyond the launch rank");
+  ProjRec p;
+  p.nin = ndim_in;
+  for (int d = 0; d < ndim_in; ++d)
+    if (keep_mask & (1u << d)) p.keep[p.nout++] = d;
+  *out = intern_proj(*c, p);
+  return DFX_OK;
+}
+
+int dfx_part_none(dfx_ctx* c, dfx_part* out) {
+  if (!c || !out) return DFX_EINVAL;
+  PartRec p;
+  p.kind = PK_NONE;
+  *out = intern_part(*c, p);
+  return DFX_OK;
+}
+
+int dfx_part_tiling(dfx_ctx* c, int32_t ndim, const int64_t* tile, const int64_t* offset, dfx_proj proj,
+                    dfx_part* out) {
+  if (!c || !out || ndim < 0 || ndim > DFX_MAX_DIM || (ndim > 0 && (!tile || !offset))) return DFX_EINVAL;
+  if (proj < 0 || proj >= (int)c->projs.size()) return fail(*c, DFX_ENOTFOUND, "unknown projection");
+  if (c->projs[proj].nout != ndim) return fail(*c, DFX_EINVAL, "projection output rank differs from tile rank");
+  PartRec p;
+  p.kind = PK_TILING;
+  p.ndim = ndim;
+  for (int k = 0; k < ndim; ++k) {
+    if (tile[k] < 0) return fail(*c, DFX_EINVAL, "negative tile extent");
+    p.tile[k] = tile[k];
+    p.off[k] = offset[k];
+  }
+  p.proj = proj;
+  *out = intern_part(*c, p);
+  return DFX_OK;
+}
+
+int dfx_part_image(dfx_ctx* c, dfx_store src, dfx_part src_part, dfx_part* out) {
+  if (!c || !out) return DFX_EINVAL;
+  if (!find_store(c, src)) return fail(*c, DFX_ENOTFOUND, "unknown source store");
+  if (src_part < 0 || src_part >= (int)c->parts.size()) return fail(*c, DFX_ENOTFOUND, "unknown partition");
+  if (c->parts[src_part].kind == PK_IMAGE) return fail(*c, DFX_EINVAL, "nested Image partitions");
+  PartRec p;
+  p.kind = PK_IMAGE;
+  p.img_src = src;
+  p.img_part = src_part;
+  *out = intern_part(*c, p);
+  return DFX_OK;
+}
+
+int dfx_submit(dfx_ctx* c, const dfx_task* task) {
+  if (!c || !task) return DFX_EINVAL;
+  TaskRec t;
+  t.op = task->op;
+  t.ndim = task->ndim;
+  if (t.ndim < 0 || t.ndim > DFX_MAX_DIM || (t.ndim > 0 && !task->launch))
+    return fail(*c, DFX_EINVAL, "bad launch domain");
+  for (int k = 0; k < t.ndim; ++k) t.launch[k] = task->launch[k];
+  if (task->nargs < 0 || (task->nargs > 0 && !task->args) || task->nimm < 0 || (task->nimm > 0 && !task->imm))
+    return fail(*c, DFX_EINVAL, "bad argument lists");
+  for (int i = 0; i < task->nargs; ++i) t.args.push_back({task->args[i].store, task->args[i].part, task->args[i].priv});
+  for (int i = 0; i < task->nimm; ++i) t.imm.push_back(task->imm[i]);
+  int rc = validate(*c, t);
+  if (rc) return rc;
+  t.seq = c->next_seq++;
+  std::set<int64_t> seen;
+  for (auto& a : t.args)
+    if (seen.insert(a.store).second) c->stores.at(a.store).pending += 1;
+  c->window.push_back(std::move(t));
+  c->stats.tasks_submitted += 1;
+  if ((int)c->window.size() >= c->cfg.window_size) return dispatch_one(*c);
+  return DFX_OK;
+}
+
+int dfx_flush(dfx_ctx* c) { return c ? flush(*c) : DFX_EINVAL; }
+
+int dfx_sync(dfx_ctx* c) {
+  if (!c) return DFX_EINVAL;
+  int rc = flush(*c);
+  if (rc) return rc;
+  if (!c->analysis_only) HIPCHK(*c, hipStreamSynchronize(c->stream));
+  return DFX_OK;
+}
+
+int dfx_graph_begin(dfx_ctx* c) {
+  if (!c) return DFX_EINVAL;
+  if (c->analysis_only) return fail(*c, DFX_ESTATE, "analysis-only context");
+  if (c->capturing) return fail(*c, DFX_ESTATE, "already recording");
+  int rc = flush(*c);
+  if (rc) return rc;
+  if (!c->stream) return fail(*c, DFX_ESTATE, "graphs need an explicit stream");
+  HIPCHK(*c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  c->capture_launches = 0;
+  c->capture_bytes = 0;
+  return DFX_OK;
+}
+
+int dfx_graph_end(dfx_ctx* c, int32_t* graph_id) {
+  if (!c || !graph_id) return DFX_EINVAL;
+  if (!c->capturing) return fail(*c, DFX_ESTATE, "not recording");
+  int rc = flush(*c);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->capturing = false;
+  if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(*c, DFX_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  std::unique_ptr<Graph> G(new Graph());
+  G->graph = g;
+  e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(g); return fail(*c, DFX_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
+  G->launches = c->capture_launches;
+  G->alg_bytes = c->capture_bytes;
+  c->graphs.push_back(std::move(G));
+  *graph_id = (int32_t)c->graphs.size() - 1;
+  return DFX_OK;
+}
+
+int dfx_graph_launch(dfx_ctx* c, int32_t id) {
+  if (!c) return DFX_EINVAL;
+  if (id < 0 || id >= (int)c->graphs.size() || !c->graphs[id]) return fail(*c, DFX_ENOTFOUND, "unknown graph");
+  int rc = flush(*c);
+  if (rc) return rc;
+  HIPCHK(*c, hipGraphLaunch(c->graphs[id]->exec, c->stream));
+  c->stats.graph_replays += 1;
+  c->stats.launches += c->graphs[id]->launches;
+  c->stats.alg_bytes += c->graphs[id]->alg_bytes;
+  return DFX_OK;
+}
+
+int dfx_graph_destroy(dfx_ctx* c, int32_t id) {
+  if (!c) return DFX_EINVAL;
+  if (id < 0 || id >= (int)c->graphs.size() || !c->graphs[id]) return fail(*c, DFX_ENOTFOUND, "unknown graph");
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipGraphExecDestroy(c->graphs[id]->exec);
+  (void)hipGraphDestroy(c->graphs[id]->graph);
+  c->graphs[id].reset();
+  return DFX_OK;
+}
+
+int dfx_stats_get(dfx_ctx* c, dfx_stats* out) {
+  if (!c || !out) return DFX_EINVAL;
+  *out = c->stats;
+  return DFX_OK;
+}
+
+int dfx_stats_reset(dfx_ctx* c) {
+  if (!c) return DFX_EINVAL;
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  c->groups.clear();
+  return DFX_OK;
+}
+
+int dfx_group_count(dfx_ctx* c, int64_t* n) {
+  if (!c || !n) return DFX_EINVAL;
+  *n = (int64_t)c->groups.size();
+  return DFX_OK;
+}
+
+int dfx_group_get(dfx_ctx* c, int64_t i, dfx_group_info* out) {
+  if (!c || !out) return DFX_EINVAL;
+  if (i < 0 || i >= (int64_t)c->groups.size()) return fail(*c, DFX_ENOTFOUND, "group index out of range");
+  *out = c->groups[i];
+  return DFX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Host-side data structures of the fused task-stream executor.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <deque>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dfx.h"
+#include "vm.h"
+
+namespace dfx {
+
+int launch_vm(const VmParams& P, int is_f64, int heavy, hipStream_t stream);
+int stream_bucket(int n_in);
+
+enum PartKind { PK_NONE = 0, PK_TILING = 1, PK_IMAGE = 2 };
+
+// Store(id, shape) of section 3.1, with split reference counts (section 5.1).
+struct StoreRec {
+  int64_t id = 0;
+  int ndim = 0;
+  int64_t shape[DFX_MAX_DIM] = {0, 0, 0, 0};
+  int dtype = DFX_F64;
+  int64_t elems = 1;
+  size_t bytes = 0;
+  void* ptr = nullptr;
+  bool external = false;
+  int app_refs = 1;     // references held by the application
+  int pending = 0;      // references held by tasks still in the window
+};
+
+struct ProjRec {
+  int nin = 0, nout = 0;
+  int keep[DFX_MAX_DIM] = {0, 0, 0, 0};  // launch dim feeding store dim k
+};
+
+// Partitions are interned: two partitions are equal iff their handles are
+// equal, an O(1) test (section 3.1, section 4.2's alias check).
+struct PartRec {
+  int kind = PK_NONE;
+  int ndim = 0;
+  int64_t tile[DFX_MAX_DIM] = {0, 0, 0, 0};
+  int64_t off[DFX_MAX_DIM] = {0, 0, 0, 0};
+  int proj = -1;
+  int64_t img_src = -1;
+  int img_part = -1;
+};
+
+struct ArgRec {
+  int64_t store;
+  int part;
+  int priv;
+};
+
+struct TaskRec {
+  uint32_t op = 0;
+  int ndim = 0;
+  int64_t launch[DFX_MAX_DIM] = {1, 1, 1, 1};
+  std::vector<ArgRec> args;
+  std::vector<double> imm;
+  int64_t seq = 0;
+};
+
+enum OpKind { K_UNARY, K_BINARY, K_IMM, K_FILL, K_AXPY, K_RED, K_SPMV };
+
+struct OpInfo {
+  uint32_t op;
+  const char* name;
+  OpKind kind;
+  int nargs;
+  int vm;        // VmOp for elementwise kinds
+};
+
+// ---- plans ------------------------------------------------------------------
+// A plan is built from a canonical window prefix: stores are referred to by
+// their canonical index (order of first appearance in the window).
+struct PStream {
+  int cstore;
+  int64_t off;          // element offset of the stream's (0, 0) element
+  int64_t s_row, s_col;
+};
+
+struct PassPlan {
+  int kind = 0;          // 0 elementwise/reduction, 1 SpMV, 2 single task
+  int dtype = DFX_F64;
+  int is1d = 1;
+  int64_t rows = 1, cols = 1, n1d = 1;
+  int64_t n_tiles = 0, strips = 1, tiles_per_wave = 1;
+  int grid = 1;
+  int heavy = 0;
+  int unit_cols = 1;
+  std::vector<PStream> ins;
+  std::vector<PStream> outs;
+  std::vector<uint8_t> out_reg;
+  std::vector<int> bc_cstore;
+  std::vector<uint8_t> bc_reg;
+  std::vector<int> red_cstore;
+  std::vector<int> red_init;
+  int spmv_rowptr = -1, spmv_col = -1, spmv_val = -1, spmv_x = -1;
+  std::vector<VmInstr> code;
+  std::vector<double> imm;
+  int64_t alg_bytes = 0;
+  // per-plan device workspace: reduction tile sums and the finish counter
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+struct Plan {
+  int prefix = 0;
+  std::vector<int> temps;   // canonical indices of eliminated stores
+  std::vector<PassPlan> passes;
+  int64_t alg_bytes = 0;
+};
+
+struct Graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t launches = 0;
+  int64_t alg_bytes = 0;
+};
+
+struct Ctx {
+  dfx_config cfg{};
+  hipStream_t stream = nullptr;
+  bool analysis_only = false;
+  std::string err;
+
+  int64_t next_store = 1;
+  std::unordered_map<int64_t, StoreRec> stores;
+  std::vector<ProjRec> projs;
+  std::unordered_map<std::string, int> proj_index;
+  std::vector<PartRec> parts;
+  std::unordered_map<std::string, int> part_index;
+
+  std::deque<TaskRec> window;
+  int64_t next_seq = 0;
+
+  std::unordered_map<std::string, std::unique_ptr<Plan>> memo;
+  std::vector<dfx_group_info> groups;
+
+  bool capturing = false;
+  int64_t capture_launches = 0, capture_bytes = 0;
+  std::vector<std::unique_ptr<Graph>> graphs;
+
+  dfx_stats stats{};
+};
+
+}  // namespace dfx

@@ -1,0 +1,91 @@
+// Kernel-side description of one fused pass, shared by the host planner and
+// the HIP executor.  Plain data only: it is passed by value as the kernel
+// argument block.
+#pragma once
+#include <stdint.h>
+
+namespace dfx {
+
+constexpr int VM_NREG = 16;     // virtual registers per element slot (transcendental kernels)
+constexpr int VM_NREG_LIGHT = 8; // register file of the arithmetic-only kernels
+constexpr int VM_E = 4;         // element slots per lane per step
+constexpr int VM_MAXIN = 10;    // input streams
+constexpr int VM_MAXOUT = 6;    // output streams
+constexpr int VM_MAXBC = 8;     // broadcast 0-d inputs
+constexpr int VM_MAXRED = 4;    // reductions per pass
+constexpr int VM_MAXCODE = 112; // instructions per pass
+constexpr int VM_MAXIMM = 24;   // immediates per pass
+// The SpMV row result lands in the last register of the file (NR - 1).
+
+// Canonical reduction tiling.  The iteration space is a set of rows of at
+// most TW elements (a 2-D space's rows, or a 1-D space cut into rows of TW);
+// a tile is RED_TH consecutive rows of one TW-wide column strip.  Lane l of
+// the wave that owns a tile holds columns [l*V, l*V+V) of the strip and
+// accumulates its elements sequentially, rows ascending then columns; the 64
+// lane sums are combined by an xor butterfly (32, 16, 8, 4, 2, 1), and the
+// tile sums by a pairwise power-of-two tree over the tile index.  V = 16
+// bytes / element size.  Nothing here depends on the launch configuration.
+constexpr int RED_TH = 32;
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int FINAL_CHUNK = 2048;  // tree level width processed in LDS (power of two)
+
+template <typename T> struct Lanes;
+template <> struct Lanes<double> { static constexpr int V = 2, U = 2, TW = WAVE * 2; };
+template <> struct Lanes<float> { static constexpr int V = 4, U = 1, TW = WAVE * 4; };
+
+enum VmOp : uint8_t {
+  VO_MOV = 0, VO_NEG, VO_ABS, VO_SQUARE, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_MAX, VO_MIN,
+  VO_ADDI, VO_SUBI, VO_RSUBI, VO_MULI, VO_DIVI, VO_RDIVI, VO_FILL,
+  VO_RED, VO_REDPROD,
+  // ops below need the transcendental kernel variant
+  VO_SQRT, VO_EXP, VO_LOG, VO_ERF, VO_POW,
+  VO_COUNT
+};
+constexpr int VO_FIRST_HEAVY = VO_SQRT;
+
+enum VmFlag : uint8_t {
+  VF_A_ACC = 1,   // operand a is the previous instruction's result
+  VF_B_ACC = 2,   // operand b is the previous instruction's result
+  VF_WB = 4       // write the result to register dst
+};
+
+struct VmInstr {
+  uint8_t op, dst, a, b;
+  uint8_t flags, slot;  // slot: reduction slot for VO_RED / VO_REDPROD
+  uint16_t imm;         // immediate index
+};
+
+struct VmStream {
+  const void* base;     // address of the element at row 0, column 0
+  int64_t s_row, s_col; // element strides
+};
+
+struct VmParams {
+  int32_t n_code, n_in, n_out, n_bc, n_red;
+  int32_t is1d;         // 1: space of n1d elements cut into rows of TW
+  int32_t spmv;         // 1: row result of y = A x lands in VM_SPMV_REG first
+  int32_t grid;         // blocks launched
+  int32_t unit_cols;    // every stream has column stride 1 (padding slots 0)
+  int64_t rows, cols;   // 2-D space; for 1-D: rows = ceil(n1d / TW), cols = TW
+  int64_t n1d;
+  int64_t n_tiles, strips;  // tiles, tiles per tile-row
+  int64_t tiles_per_wave;
+  VmStream in[VM_MAXIN];
+  VmStream out[VM_MAXOUT];
+  uint8_t out_reg[VM_MAXOUT];
+  uint8_t bc_reg[VM_MAXBC];
+  const void* bc[VM_MAXBC];
+  void* red_partials[VM_MAXRED];   // n_tiles entries each
+  void* red_result[VM_MAXRED];     // 0-d store
+  int32_t red_init[VM_MAXRED];
+  unsigned int* counter;           // blocks finished (reset by the last block)
+  const int32_t* rowptr;           // SpMV operands
+  const int32_t* colidx;
+  const void* val;
+  const void* x;
+  double imm[VM_MAXIMM];
+  VmInstr code[VM_MAXCODE];
+};
+
+}  // namespace dfx
