@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused task-window executor on one MI355X.
+
+Headline workload: Black-Scholes over 2^26 options in FP64.  A step is one
+pass of the whole hot path over that batch: 28 index tasks submitted through
+the C ABI, the window analysed (memoised after the first pass), and the fused
+group executed as one kernel.  Inputs are resident in HBM before timing.
+
+Printed: one JSON line with the headline (fused algorithmic HBM GB/s), the
+roofline of the dominant kernel, the CPU oracle timed on a bounded sample,
+and the other legs of the metric (unfused GB/s, FP32, Jacobi stencil, CG
+iterations/s) under "legs".  Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2406_18109_amd/csrc/kernels.hip", "paper_2406_18109_amd/csrc/vm.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name, per_launch_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    e = d.get(name)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def timed_steps(torch, stream, step, K):
+    """Run K steps between synchronisations; return (wall ms per step, list of
+    per-step event ms on the executor's stream)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        evs[i][0].record(stream)
+        step()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / K
+    return wall, [a.elapsed_time(b) for a, b in evs]
+
+
+class BSBench:
+    def __init__(self, dfx, synth, wl, np, n, dtype, fuse):
+        self.np = np
+        npdt = np.float64 if dtype == "f64" else np.float32
+        self.ctx = dfx.Context(device=0, window_size=64, fuse=fuse)
+        self.dfx, self.n, self.dtype = dfx, n, dtype
+        S, K, T = synth.bs_inputs(n, npdt)
+        r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL, npdt)
+        c = self.ctx
+        self.h = []
+        for a in (S, K, T):
+            s = c.store_create([n], dtype)
+            c.store_write(s, a)
+            self.h.append(s)
+        for v in (r, sig, rv):
+            s = c.store_create([], dtype)
+            c.store_write(s, np.array(v, dtype=npdt))
+            self.h.append(s)
+        self.out = None
+        del S, K, T
+
+    def step(self):
+        c = self.ctx
+        if self.out:
+            c.store_release(self.out[0])
+            c.store_release(self.out[1])
+        S, K, T, r, sig, rv = self.h
+        self.out = self.dfx.apps.black_scholes(c, S, K, T, r, sig, rv, self.n, self.dtype)
+        c.flush()
+
+    def close(self):
+        self.ctx.close()
+
+
+def bs_leg(torch, dfx, synth, wl, np, n, dtype, fuse, K, W):
+    b = BSBench(dfx, synth, wl, np, n, dtype, fuse)
+    for _ in range(W):
+        b.step()
+    b.ctx.stats_reset()
+    wall, ev = timed_steps(torch, b.ctx.torch_stream, b.step, K)
+    st = b.ctx.stats()
+    bytes_per_step = st["alg_bytes"] / K
+    launches = st["launches"] / K
+    b.close()
+    ev_ms = sum(ev) / len(ev)
+    return {"ms_per_step": wall, "event_ms_per_step": ev_ms, "alg_bytes_per_step": bytes_per_step,
+            "launches_per_step": launches, "gbs": bytes_per_step / (wall * 1e-3) / 1e9,
+            "kernel_gbs": bytes_per_step / (ev_ms * 1e-3) / 1e9}
+
+
+def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
+    c = dfx.Context(device=0, window_size=16, fuse=fuse)
+    G = c.store_create([N, N], "f64")
+    c.store_write(G, synth.jacobi_grid(N))
+    J = dfx.apps.Jacobi(c, G, N)
+    for _ in range(3):
+        J.sweep()
+    c.sync()
+    c.stats_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        J.sweep()
+    c.sync()
+    dt = (time.perf_counter() - t0) / sweeps
+    st = c.stats()
+    out = {"ms_per_sweep": dt * 1e3, "alg_bytes_per_sweep": st["alg_bytes"] / sweeps,
+           "gbs": st["alg_bytes"] / sweeps / dt / 1e9, "launches_per_sweep": st["launches"] / sweeps}
+    c.close()
+    return out
+
+
+def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
+    c = dfx.Context(device=0, window_size=16, fuse=fuse)
+    rowptr, col, val = synth.poisson_csr(m, dim)
+    n = m ** dim
+    b = synth.rhs(n, synth.CG64_SEED if dim == 2 else synth.CG256_SEED)
+    hs = []
+    for a, dt in ((rowptr, "i32"), (col, "i32"), (val, "f64"), (b, "f64")):
+        s = c.store_create(list(a.shape), dt)
+        c.store_write(s, a)
+        hs.append(s)
+    del rowptr, col, val
+    cg = dfx.apps.CG(c, *hs, n)
+    for _ in range(2):
+        cg.iteration()
+    c.sync()
+    g = None
+    if graph:
+        c.graph_begin()
+        cg.iteration()
+        g = c.graph_end()
+    c.sync()
+    c.stats_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        if g is not None:
+            c.graph_launch(g)
+        else:
+            cg.iteration()
+    c.sync()
+    dt = (time.perf_counter() - t0) / iters
+    st = c.stats()
+    out = {"iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
+           "alg_bytes_per_iter": st["alg_bytes"] / iters,
+           "gbs": st["alg_bytes"] / iters / dt / 1e9, "launches_per_iter": st["launches"] / iters}
+    if g is not None:
+        c.graph_destroy(g)
+    c.close()
+    return out
+
+
+def cpu_baseline(synth, wl, np, sample):
+    S, K, T = synth.bs_inputs(sample)
+    r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL)
+    wl.black_scholes(S[:1000], K[:1000], T[:1000], r, sig, rv)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        wl.black_scholes(S, K, T, r, sig, rv)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return sample * 40 / dt / 1e9, reps, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default="all", help="all | headline")
+    ap.add_argument("--log2n", type=int, default=26)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (the executor runs on "
+              "a single device)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2406_18109_amd as dfx
+    import synth
+    from oracle import workloads as wl
+
+    n = 1 << args.log2n
+    K, W = args.steps, args.warmup
+    log("black-scholes f64 fused n=2^%d" % args.log2n)
+    fused = bs_leg(torch, dfx, synth, wl, np, n, "f64", True, K, W)
+    log("fused", fused)
+    legs = {"bs_f64_fused": fused}
+    if args.legs == "all":
+        log("black-scholes f64 unfused")
+        legs["bs_f64_unfused"] = bs_leg(torch, dfx, synth, wl, np, n, "f64", False, max(2, K // 5), 1)
+        log("black-scholes f32 fused / unfused")
+        legs["bs_f32_fused"] = bs_leg(torch, dfx, synth, wl, np, n, "f32", True, K, W)
+        legs["bs_f32_unfused"] = bs_leg(torch, dfx, synth, wl, np, n, "f32", False, max(2, K // 5), 1)
+        log("jacobi 8192^2 fused / unfused")
+        legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, 20, True)
+        legs["jacobi_unfused"] = jacobi_leg(torch, dfx, synth, np, 8192, 5, False)
+        log("cg 64^2")
+        legs["cg64_unfused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, False, False)
+        legs["cg64_fused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, False)
+        legs["cg64_fused_graph"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, True)
+        log("cg 256^3")
+        legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
+        legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
+        for a, b in (("bs_f64_fused", "bs_f64_unfused"), ("bs_f32_fused", "bs_f32_unfused")):
+            legs[a]["speedup_vs_unfused"] = legs[b]["ms_per_step"] / legs[a]["ms_per_step"]
+        legs["jacobi_fused"]["speedup_vs_unfused"] = legs["jacobi_unfused"]["ms_per_sweep"] / legs["jacobi_fused"]["ms_per_sweep"]
+
+    log("cpu oracle sample")
+    sample = 1 << 21
+    cpu_gbs, reps, dt = cpu_baseline(synth, wl, np, sample)
+    per_launch = fused["alg_bytes_per_step"] / max(1.0, fused["launches_per_step"])
+    achieved = per_launch / (fused["event_ms_per_step"] * 1e-3) / 1e9
+    traffic = measured_traffic("bs_f64_fused", per_launch)
+    line = {
+        "metric": "fused vs unfused HBM GB/s (% of peak) and CG iters/s on 1 MI355X; p99 solve latency",
+        "value": round(fused["gbs"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(fused["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "black-scholes fused pass, 2^%d options FP64 (28 index tasks -> 1 kernel)" % args.log2n,
+                   "options": n, "tasks_per_pass": 28, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "cpu_baseline": {"value": round(cpu_gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                         "sample": "%d options x %d reps, FP64 numpy + libm, unfused op by op" % (sample, reps)},
+        "legs": legs,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -835,10 +835,14 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
       }
     }
     if (has_spmv && busy_until[NR - 1] < -1) busy_until[NR - 1] = -1;
+    // the kernel loads every slot of the stream bucket each step, so
+    // permanent registers start above the bucket
+    const int nload = stream_bucket(nin);
+    if (nload > NR) return false;
     for (size_t v = 0; v < vals.size(); ++v) {
       if (vals[v].kind != 1) continue;
       int r = -1;
-      for (int q = nin; q < NR - (has_spmv ? 1 : 0); ++q)
+      for (int q = nload; q < NR - (has_spmv ? 1 : 0); ++q)
         if (busy_until[q] == -2) { r = q; break; }
       if (r < 0) return false;
       vals[v].reg = r;

@@ -268,6 +268,8 @@ template <typename T, bool HEAVY, int NINB, int NR>
 __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   constexpr int V = Lanes<T>::V, U = Lanes<T>::U, TW = Lanes<T>::TW;
   static_assert(U * V == VM_E, "element slots");
+  // the planner never pairs a register file smaller than the stream bucket
+  if constexpr (NINB > NR) { return; } else {
 
   T r0[NR], r1[NR], r2[NR], r3[NR];
   Regs<T> G;
@@ -362,6 +364,7 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   if (threadIdx.x == 0) {
     __threadfence();
     atomicExch(P.counter, 0u);
+  }
   }
 }
 
