@@ -220,6 +220,71 @@ int dfx_stats_reset(dfx_ctx* ctx);
 int dfx_group_count(dfx_ctx* ctx, int64_t* n);
 int dfx_group_get(dfx_ctx* ctx, int64_t i, dfx_group_info* out);
 
+
+/* ---- serving: continuous batching of independent CG solves -------------- */
+/* Not in the paper: a request loop over the same arithmetic.  A scheduler
+ * thread admits queued solves while a slot is free and their HBM footprint
+ * fits `hbm_budget`, runs one CG iteration per round for every resident solve
+ * in shared launches (work items = (solve, canonical tile)), and retires
+ * solves that reach sqrt(rho_k) <= tol * ||b|| (or max_iter, or breakdown).
+ * Solves arriving while others run join at the next round.  A solve's
+ * arithmetic depends only on its own data, so its result is bit-identical
+ * alone and in any mix.  submit/poll/wait/read_x/release/stats are
+ * thread-safe with respect to the scheduler.  Matrices are FP64 CSR with I32
+ * indices; x0 = 0. */
+enum {
+  DFX_SOLVE_QUEUED = 0,
+  DFX_SOLVE_RUNNING = 1,
+  DFX_SOLVE_CONVERGED = 2,
+  DFX_SOLVE_MAXITER = 3,
+  DFX_SOLVE_BREAKDOWN = 4
+};
+
+typedef struct {
+  uint64_t hbm_budget;   /* bytes resident solves may hold at once */
+  int32_t max_slots;     /* solves resident at once */
+  int32_t max_iter;      /* iteration limit per solve */
+  double tol;            /* relative residual target */
+  int32_t reserved[8];
+} dfx_serve_cfg;
+
+/* Host CSR arrays: validated and referenced (not copied) by submit; they must
+ * stay valid until the solve leaves the QUEUED state. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* rowptr;  /* n+1 entries, rowptr[0] = 0, rowptr[n] = nnz */
+  const int32_t* col;     /* nnz entries in [0, n) */
+  const double* val;      /* nnz entries */
+} dfx_csr_desc;
+
+typedef struct {
+  int32_t status;         /* DFX_SOLVE_* */
+  int32_t iterations;
+  double rel_residual;    /* sqrt(rho)/||b|| of the recursive residual */
+  double t_arrive, t_admit, t_done;  /* steady-clock seconds */
+} dfx_solve_result;
+
+typedef struct {
+  int64_t submitted, admitted, completed, rounds, launches, iterations;
+  int64_t row_updates;    /* rows touched per CG phase, summed over rounds */
+  uint64_t peak_bytes, resident_bytes;
+  int64_t queued;
+} dfx_serve_counters;
+
+int dfx_serve_start(dfx_ctx* ctx, const dfx_serve_cfg* cfg);
+/* Queue a solve; b (n doubles) is copied.  DFX_ENOMEM_BUDGET if its
+ * footprint can never fit, DFX_EINVAL for a malformed CSR. */
+int dfx_serve_submit(dfx_ctx* ctx, const dfx_csr_desc* A, const double* b, uint64_t* ticket);
+int dfx_serve_poll(dfx_ctx* ctx, uint64_t ticket, dfx_solve_result* out);
+/* Block until the solve finishes or timeout_s passes (DFX_ESTATE on timeout). */
+int dfx_serve_wait(dfx_ctx* ctx, uint64_t ticket, double timeout_s, dfx_solve_result* out);
+int dfx_serve_read_x(dfx_ctx* ctx, uint64_t ticket, double* host, size_t n);
+int dfx_serve_release(dfx_ctx* ctx, uint64_t ticket);
+int dfx_serve_stats(dfx_ctx* ctx, dfx_serve_counters* out);
+/* Finish every queued and resident solve, then stop the scheduler. */
+int dfx_serve_stop(dfx_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

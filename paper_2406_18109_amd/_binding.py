@@ -67,6 +67,30 @@ class dfx_group_info(C.Structure):
                 ("temporaries", C.c_int64 * INFO_MAX), ("alg_bytes", C.c_int64)]
 
 
+class dfx_serve_cfg(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("reserved", C.c_int32 * 8)]
+
+
+class dfx_csr_desc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class dfx_solve_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_residual", C.c_double),
+                ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class dfx_serve_counters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rounds", C.c_int64), ("launches", C.c_int64), ("iterations", C.c_int64),
+                ("row_updates", C.c_int64), ("peak_bytes", C.c_uint64), ("resident_bytes", C.c_uint64),
+                ("queued", C.c_int64)]
+
+
+SOLVE_QUEUED, SOLVE_RUNNING, SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN = 0, 1, 2, 3, 4
+
 _lib = None
 
 # name -> (restype, argtypes) for every exported call
@@ -97,6 +121,14 @@ SIGNATURES = {
     "dfx_stats_reset": (C.c_int, [C.c_void_p]),
     "dfx_group_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "dfx_group_get": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(dfx_group_info)]),
+    "dfx_serve_start": (C.c_int, [C.c_void_p, C.POINTER(dfx_serve_cfg)]),
+    "dfx_serve_submit": (C.c_int, [C.c_void_p, C.POINTER(dfx_csr_desc), C.c_void_p, C.POINTER(C.c_uint64)]),
+    "dfx_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(dfx_solve_result)]),
+    "dfx_serve_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, C.POINTER(dfx_solve_result)]),
+    "dfx_serve_read_x": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t]),
+    "dfx_serve_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "dfx_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(dfx_serve_counters)]),
+    "dfx_serve_stop": (C.c_int, [C.c_void_p]),
 }
 
 
@@ -317,6 +349,60 @@ class Context:
 
     def stats_reset(self):
         self._chk(self.L.dfx_stats_reset(self.h))
+
+    # -- serving ------------------------------------------------------------------
+    def serve_start(self, hbm_budget: int, max_slots: int = 256, tol: float = 1e-8, max_iter: int = 100000):
+        cfg = dfx_serve_cfg(hbm_budget, max_slots, max_iter, tol)
+        self._chk(self.L.dfx_serve_start(self.h, C.byref(cfg)))
+        self._serve_keep = {}
+
+    def serve_submit(self, rowptr, col, val, b) -> int:
+        """Queue one CG solve; the CSR arrays are kept referenced until admission."""
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        n = rowptr.size - 1
+        d = dfx_csr_desc(n, col.size, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+        t = C.c_uint64()
+        self._chk(self.L.dfx_serve_submit(self.h, C.byref(d), b.ctypes.data, C.byref(t)))
+        self._serve_keep[t.value] = (rowptr, col, val)
+        return t.value
+
+    @staticmethod
+    def _res(r):
+        return {"status": r.status, "iterations": r.iterations, "rel_residual": r.rel_residual,
+                "t_arrive": r.t_arrive, "t_admit": r.t_admit, "t_done": r.t_done}
+
+    def serve_poll(self, ticket: int) -> dict:
+        r = dfx_solve_result()
+        self._chk(self.L.dfx_serve_poll(self.h, ticket, C.byref(r)))
+        if r.status != SOLVE_QUEUED:
+            self._serve_keep.pop(ticket, None)
+        return self._res(r)
+
+    def serve_wait(self, ticket: int, timeout: float = 600.0) -> dict:
+        r = dfx_solve_result()
+        self._chk(self.L.dfx_serve_wait(self.h, ticket, timeout, C.byref(r)))
+        self._serve_keep.pop(ticket, None)
+        return self._res(r)
+
+    def serve_read_x(self, ticket: int, n: int) -> np.ndarray:
+        x = np.empty(n, dtype=np.float64)
+        self._chk(self.L.dfx_serve_read_x(self.h, ticket, x.ctypes.data, n))
+        return x
+
+    def serve_release(self, ticket: int):
+        self._chk(self.L.dfx_serve_release(self.h, ticket))
+
+    def serve_stats(self) -> dict:
+        s = dfx_serve_counters()
+        self._chk(self.L.dfx_serve_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in dfx_serve_counters._fields_}
+
+    def serve_stop(self):
+        self._chk(self.L.dfx_serve_stop(self.h))
+        self._serve_keep = {}
 
     def groups(self) -> list:
         n = C.c_int64()

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
-          "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
+          "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-pthread"]
 # Device code: no packed FP32 instructions, IEEE-rounded fp32 divide/sqrt,
 # denormals kept.
 DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
@@ -28,7 +28,9 @@ DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
 
 SOURCES = [
     ("core.cpp", False),
+    ("serve.cpp", False),
     ("kernels.hip", True),
+    ("serve.hip", True),
 ]
 
 
@@ -52,7 +54,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -59,6 +59,7 @@ static bool reads(int pr) { return pr == DFX_R || pr == DFX_RW; }
 static bool writes(int pr) { return pr == DFX_W || pr == DFX_RW; }
 static bool reduces(int pr) { return pr == DFX_RD; }
 static bool heavy_op(int vm) { return vm >= VO_FIRST_HEAVY; }
+static bool pow_op(int vm) { return vm == VO_POW; }
 
 static int fail(Ctx& c, int code, const std::string& msg) {
   c.err = msg;
@@ -813,23 +814,25 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
       outs.size() > (size_t)VM_MAXOUT)
     return fail(c, DFX_EUNSUPPORTED, "fused pass exceeds the kernel's stream/op limits");
 
-  bool heavy = false;
-  for (auto& I : code) heavy = heavy || heavy_op(I.op);
+  bool heavy = false, has_pow = false;
+  for (auto& I : code) { heavy = heavy || heavy_op(I.op); has_pow = has_pow || pow_op(I.op); }
   // register allocation: inputs fixed at 0..n_in-1, SpMV result at NR-1,
-  // broadcasts in permanent registers above the inputs, computed values by
-  // linear scan (an operand's register is free for the instruction's result)
-  auto allocate = [&](int NR) -> bool {
+  // broadcasts in permanent registers above the stream bucket, computed
+  // values by linear scan (an operand's register is free for the
+  // instruction's result)
+  int tier = 0;
+  auto allocate = [&](int NR, int nload) -> bool {
     for (auto& v : vals) v.reg = -1;
     std::vector<int> busy_until(NR, -2);  // last instruction reading the register; INF permanent
     const int nin = (int)out.ins.size();
-    if (nin > NR) return false;
+    if (nin > NR || nload > NR) return false;
     const bool has_spmv = kind == 1;
     for (size_t v = 0; v < vals.size(); ++v) {
       if (vals[v].kind == 0) {
         vals[v].reg = vals[v].idx;
         busy_until[vals[v].idx] = std::max(vals[v].last_use, -1);
       } else if (vals[v].kind == 3) {
-        if (NR - 1 < nin) return false;
+        if (NR - 1 < nload) return false;
         vals[v].reg = NR - 1;
         busy_until[NR - 1] = std::max(vals[v].last_use, -1);
       }
@@ -837,8 +840,6 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     if (has_spmv && busy_until[NR - 1] < -1) busy_until[NR - 1] = -1;
     // the kernel loads every slot of the stream bucket each step, so
     // permanent registers start above the bucket
-    const int nload = stream_bucket(nin);
-    if (nload > NR) return false;
     for (size_t v = 0; v < vals.size(); ++v) {
       if (vals[v].kind != 1) continue;
       int r = -1;
@@ -860,13 +861,13 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     }
     return true;
   };
-  int NR = VM_NREG_LIGHT;
-  if (heavy || out.ins.size() > 6 || !allocate(NR)) {
-    heavy = true;
-    NR = VM_NREG;
-    if (!allocate(NR)) return fail(c, DFX_EUNSUPPORTED, "fused pass needs more than 16 live values");
-  }
-  out.heavy = heavy;
+  const int nin = (int)out.ins.size();
+  bool ok = false;
+  if (!has_pow && !heavy && nin <= 6) { tier = 0; ok = allocate(VM_NREG_LIGHT, stream_bucket(nin, 0)); }
+  if (!ok && !has_pow && nin <= 6) { tier = 1; ok = allocate(VM_NREG, stream_bucket(nin, 1)); }
+  if (!ok) { tier = 2; ok = allocate(VM_NREG, stream_bucket(nin, 2)); }
+  if (!ok) return fail(c, DFX_EUNSUPPORTED, "fused pass needs more than 16 live values");
+  out.tier = tier;
   // emit kernel instructions with operand forwarding
   out.code.clear();
   for (size_t i = 0; i < code.size(); ++i) {
@@ -1016,13 +1017,17 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   P.spmv = p.kind == 1;
   P.grid = p.grid;
   P.unit_cols = p.unit_cols;
+  {
+    const int64_t V = p.dtype == DFX_F64 ? Lanes<double>::V : Lanes<float>::V;
+    P.vec_cols = p.unit_cols && (p.is1d ? (p.n1d % V == 0) : (p.cols % V == 0));
+  }
   P.rows = p.rows;
   P.cols = p.cols;
   P.n1d = p.n1d;
   P.n_tiles = p.n_tiles;
   P.strips = p.strips;
   P.tiles_per_wave = p.tiles_per_wave;
-  const int nb = stream_bucket(P.n_in);
+  const int nb = stream_bucket(P.n_in, p.tier);
   for (int k = 0; k < VM_MAXIN; ++k) {
     if (k < P.n_in) {
       const PStream& s = p.ins[k];
@@ -1061,7 +1066,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   }
   for (size_t i = 0; i < p.imm.size(); ++i) P.imm[i] = p.imm[i];
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
-  int e = launch_vm(P, p.dtype == DFX_F64, p.heavy, c.stream);
+  int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
 }
@@ -1186,6 +1191,7 @@ int dfx_create(const dfx_config* cfg, dfx_ctx** out) {
 
 int dfx_destroy(dfx_ctx* c) {
   if (!c) return DFX_EINVAL;
+  if (c->server) (void)dfx_serve_stop(c);
   int rc = c->capturing ? DFX_OK : flush(*c);
   if (!c->analysis_only) {
     for (auto& kv : c->memo)

@@ -14,8 +14,8 @@
 
 namespace dfx {
 
-int launch_vm(const VmParams& P, int is_f64, int heavy, hipStream_t stream);
-int stream_bucket(int n_in);
+int launch_vm(const VmParams& P, int is_f64, int tier, hipStream_t stream);
+int stream_bucket(int n_in, int tier);
 
 enum PartKind { PK_NONE = 0, PK_TILING = 1, PK_IMAGE = 2 };
 
@@ -91,7 +91,7 @@ struct PassPlan {
   int64_t rows = 1, cols = 1, n1d = 1;
   int64_t n_tiles = 0, strips = 1, tiles_per_wave = 1;
   int grid = 1;
-  int heavy = 0;
+  int tier = 0;          // kernel tier: 0 arithmetic, 1 transcendental, 2 with pow
   int unit_cols = 1;
   std::vector<PStream> ins;
   std::vector<PStream> outs;
@@ -147,6 +147,7 @@ struct Ctx {
   std::vector<std::unique_ptr<Graph>> graphs;
 
   dfx_stats stats{};
+  void* server = nullptr;   // continuous-batching CG server, if started
 };
 
 }  // namespace dfx

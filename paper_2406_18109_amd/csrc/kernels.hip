@@ -13,6 +13,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "dev_common.h"
 #include "vm.h"
 
 namespace dfx {
@@ -36,119 +37,180 @@ template <> __device__ __forceinline__ float d_pow<float>(float x, float y) { re
 template <typename T> __device__ __forceinline__ T d_max(T x, T y) { return (x > y || x != x) ? x : y; }
 template <typename T> __device__ __forceinline__ T d_min(T x, T y) { return (x < y || x != x) ? x : y; }
 
-template <typename T> __device__ __forceinline__ T shfl_xor(T v, int m);
-template <> __device__ __forceinline__ double shfl_xor<double>(double v, int m) { return __shfl_xor(v, m, WAVE); }
-template <> __device__ __forceinline__ float shfl_xor<float>(float v, int m) { return __shfl_xor(v, m, WAVE); }
-
-// Fixed xor butterfly: every lane ends with the same value (IEEE addition
-// is commutative, so lane l and lane l^m compute the identical sum).
-template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int m = WAVE / 2; m >= 1; m >>= 1) v = v + shfl_xor(v, m);
-  return v;
-}
-
-// Pairwise power-of-two tree over a[0..L) in LDS: level h adds a[i+h] into
-// a[i] for i a multiple of 2h with i+h < L.  Result in a[0].
-template <typename T> __device__ void lds_tree(T* a, int L) {
-  for (int h = 1; h < L; h <<= 1) {
-    for (int i = threadIdx.x * 2 * h; i < L; i += BLOCK * 2 * h)
-      if (i + h < L) a[i] = a[i] + a[i + h];
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__device__ T row_spmv(const VmParams& P, int64_t i) {
-  const int32_t b = P.rowptr[i], e = P.rowptr[i + 1];
-  const T* val = (const T*)P.val;
-  const T* x = (const T*)P.x;
-  T s = (T)0;
-  if (b < e) {
-    s = val[b] * x[P.colidx[b]];
-    for (int32_t k = b + 1; k < e; ++k) {
-      const T t = val[k] * x[P.colidx[k]];
-      s = s + t;
-    }
-  }
-  return s;
-}
-
-// Register file: one array of VM_NREG per element slot, indexed only by
-// wave-uniform values, so the compiler keeps each in VGPRs and reaches it with
-// indexed moves.
+// Register file: one array of NR registers per element slot, indexed only by
+// wave-uniform values, so the compiler keeps each array in VGPRs and reaches
+// it with indexed moves.  Slots 2 and 3 exist only when E == 4.
 template <typename T> struct Regs {
   T z0, z1, z2, z3;         // previous instruction's result (forwarded operand)
   T acc0, acc1, acc2, acc3; // this lane's reduction accumulators
 };
+
+template <typename T, int HV, bool SPMV> struct Shape {
+  static constexpr bool HEAVY = HV > 0;
+  static constexpr int V = Lanes<T>::V;
+  static constexpr int TW = Lanes<T>::TW;
+  // FP64 arithmetic-only passes take two rows per step; passes with
+  // transcendental ops or an SpMV prologue take one, to keep the register
+  // footprint (and occupancy) in check.  Rows are visited in order either
+  // way, so the canonical reduction order does not depend on U.
+  static constexpr int U = (sizeof(T) == 8 && !HEAVY && !SPMV) ? 2 : 1;
+  static constexpr int E = U * V;
+  static constexpr int NR = HEAVY ? VM_NREG : VM_NREG_LIGHT;
+};
+
 #define DFX_RF T (&r0)[NR], T (&r1)[NR], T (&r2)[NR], T (&r3)[NR]
 
-// One step: U rows of the tile, V columns per lane.  FAST: every slot of
-// every lane is in range and every stream has unit column stride, so each
-// stream is NINB vector loads issued back to back; otherwise per-element
-// masked loads.  NINB is the stream bucket: slots n_in..NINB-1 read a
-// harmless broadcast address.
-template <typename T, bool HEAVY, int NINB, int NR>
-__device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, int64_t row0, int64_t c0,
-                                         unsigned vmask, const bool FAST) {
-  constexpr int V = Lanes<T>::V, U = Lanes<T>::U, TW = Lanes<T>::TW;
+enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
+
+// y = A x for the rows of the step's slots: each row is summed sequentially
+// in CSR order; four nonzeros of every slot are fetched per round so that
+// several gathers are in flight.
+template <typename T, int E, int U, int V, int TW>
+__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t row0, int64_t c0, unsigned vmask,
+                                          T (&out)[4]) {
+  const T* val = (const T*)P.val;
+  const T* x = (const T*)P.x;
+  int32_t rb[E], re[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int u = e / V, v = e % V;
+    const bool ok = (vmask >> e) & 1;
+    const int64_t i = ok ? (row0 + u) * TW + c0 + v : 0;
+    rb[e] = P.rowptr[i];
+    re[e] = ok ? P.rowptr[i + 1] : rb[e];
+  }
+  int kmax = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) kmax = max(kmax, re[e] - rb[e]);
+  T s[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) s[e] = (T)0;
+  for (int k = 0; k < kmax; k += 4) {
+    int32_t cidx[E][4];
+    T a[E][4], xv[E][4];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t idx = rb[e] + k + j;
+        const bool ok = idx < re[e];
+        cidx[e][j] = ok ? P.colidx[ok ? idx : 0] : 0;
+        a[e][j] = val[ok ? idx : 0];
+      }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[e][j] = x[cidx[e][j]];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (rb[e] + k + j < re[e]) {
+          const T t = a[e][j] * xv[e][j];
+          s[e] = (k + j == 0) ? t : s[e] + t;
+        }
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[e] = s[e];
+}
+
+// One step: U rows of the tile, V columns per lane.
+//   MODE_FAST : every slot of every lane valid, unit column strides: vector
+//               loads of all streams issued back to back.
+//   MODE_CLAMP: validity is whole V-vectors (unit strides, widths multiple
+//               of V): the same vector loads with invalid lanes pointed at
+//               the stream's first element and zeroed.
+//   MODE_SLOW : per-element masked accesses, one stream at a time.
+// Slots n_in..NINB-1 of the bucket read a 4 KB zero page in the vector modes.
+template <typename T, int HV, bool SPMV, int NINB>
+__device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, SPMV>::NR],
+                                         T (&r1)[Shape<T, HV, SPMV>::NR], T (&r2)[Shape<T, HV, SPMV>::NR],
+                                         T (&r3)[Shape<T, HV, SPMV>::NR], Regs<T>& G, int64_t row0,
+                                         int64_t c0, unsigned vmask, const int mode) {
+  typedef Shape<T, HV, SPMV> S;
+  constexpr bool HEAVY = S::HEAVY;
+  constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, NR = S::NR;
+  static_assert(E == 2 || E == 4, "element slots");
   typedef T vecA __attribute__((ext_vector_type(V), aligned(sizeof(T))));
 
-  // ---- loads: all issued before the first use --------------------------------
-  T L[NINB][VM_E];
+  // ---- loads: every load of the step in flight before the first wait --------
+  if (mode != MODE_SLOW) {
+    T L[NINB][E];
+    bool okv[U];
 #pragma unroll
-  for (int a = 0; a < NINB; ++a) {
-    const T* b = (const T*)P.in[a].base;
-    const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;
-    if (FAST) {
-      // sc is 1 for real streams and 0 for padding slots
-      const int64_t cc = c0 & (-sc);
+    for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      const T* b = (const T*)P.in[a].base;
+      // column stride is 1 for real streams and 0 for padding slots
+      const int64_t cc = c0 & (-P.in[a].s_col);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const vecA w = *(const vecA*)(b + (row0 + u) * sr + cc);
+        const T* p = b + (row0 + u) * P.in[a].s_row + cc;
+        if (mode == MODE_CLAMP) p = okv[u] ? p : b;
+        const vecA w = *(const vecA*)p;
 #pragma unroll
         for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
       }
-    } else {
+    }
+    if (mode == MODE_CLAMP) {
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int a = 0; a < NINB; ++a)
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const bool ok = (vmask >> (u * V + v)) & 1;
-          const T w = b[ok ? (row0 + u) * sr + (c0 + v) * sc : 0];
-          L[a][u * V + v] = ok ? w : (T)0;
-        }
+        for (int e = 0; e < E; ++e) L[a][e] = ((vmask >> e) & 1) ? L[a][e] : (T)0;
+    }
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      r0[a] = L[a][0]; r1[a] = L[a][1];
+      if constexpr (E == 4) { r2[a] = L[a][2]; r3[a] = L[a][3]; }
+    }
+  } else {
+    for (int a = 0; a < P.n_in; ++a) {
+      const T* b = (const T*)P.in[a].base;
+      const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;
+      T w[4];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int u = e / V, v = e % V;
+        const bool ok = (vmask >> e) & 1;
+        const T q = b[ok ? (row0 + u) * sr + (c0 + v) * sc : 0];
+        w[e] = ok ? q : (T)0;
+      }
+      r0[a] = w[0]; r1[a] = w[1];
+      if constexpr (E == 4) { r2[a] = w[2]; r3[a] = w[3]; }
     }
   }
-#pragma unroll
-  for (int a = 0; a < NINB; ++a) {
-    r0[a] = L[a][0]; r1[a] = L[a][1]; r2[a] = L[a][2]; r3[a] = L[a][3];
-  }
-  if (P.spmv) {
-    T e[VM_E];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int64_t i = (row0 + u) * TW + c0 + v;
-        e[u * V + v] = ((vmask >> (u * V + v)) & 1) ? row_spmv<T>(P, i) : (T)0;
-      }
-    r0[NR - 1] = e[0]; r1[NR - 1] = e[1]; r2[NR - 1] = e[2]; r3[NR - 1] = e[3];
+  if constexpr (SPMV) {
+    T y[4];
+    spmv_rows<T, E, U, V, TW>(P, row0, c0, vmask, y);
+    r0[NR - 1] = y[0]; r1[NR - 1] = y[1];
+    if constexpr (E == 4) { r2[NR - 1] = y[2]; r3[NR - 1] = y[3]; }
   }
 
   // ---- op list ----------------------------------------------------------------
   for (int pc = 0; pc < P.n_code; ++pc) {
     const VmInstr I = P.code[pc];
     const int d = I.dst, ia = I.a, ib = I.b;
-    T x0, x1, x2, x3, y0, y1, y2, y3;
-    if (I.flags & VF_A_ACC) { x0 = G.z0; x1 = G.z1; x2 = G.z2; x3 = G.z3; }
-    else { x0 = r0[ia]; x1 = r1[ia]; x2 = r2[ia]; x3 = r3[ia]; }
-    if (I.flags & VF_B_ACC) { y0 = G.z0; y1 = G.z1; y2 = G.z2; y3 = G.z3; }
-    else { y0 = r0[ib]; y1 = r1[ib]; y2 = r2[ib]; y3 = r3[ib]; }
+    T x0, x1, x2 = 0, x3 = 0, y0, y1, y2 = 0, y3 = 0;
+    if (I.flags & VF_A_ACC) {
+      x0 = G.z0; x1 = G.z1;
+      if constexpr (E == 4) { x2 = G.z2; x3 = G.z3; }
+    } else {
+      x0 = r0[ia]; x1 = r1[ia];
+      if constexpr (E == 4) { x2 = r2[ia]; x3 = r3[ia]; }
+    }
+    if (I.flags & VF_B_ACC) {
+      y0 = G.z0; y1 = G.z1;
+      if constexpr (E == 4) { y2 = G.z2; y3 = G.z3; }
+    } else {
+      y0 = r0[ib]; y1 = r1[ib];
+      if constexpr (E == 4) { y2 = r2[ib]; y3 = r3[ib]; }
+    }
     const T k = (T)P.imm[I.imm];
-    T z0, z1, z2, z3;
-#define BIN(EXPR) { z0 = EXPR(x0, y0); z1 = EXPR(x1, y1); z2 = EXPR(x2, y2); z3 = EXPR(x3, y3); } break;
-#define UN(EXPR) { z0 = EXPR(x0); z1 = EXPR(x1); z2 = EXPR(x2); z3 = EXPR(x3); } break;
+    T z0, z1, z2 = 0, z3 = 0;
+#define BIN(EXPR) { z0 = EXPR(x0, y0); z1 = EXPR(x1, y1); if constexpr (E == 4) { z2 = EXPR(x2, y2); z3 = EXPR(x3, y3); } } break;
+#define UN(EXPR) { z0 = EXPR(x0); z1 = EXPR(x1); if constexpr (E == 4) { z2 = EXPR(x2); z3 = EXPR(x3); } } break;
 #define F_ADD(a, b) ((a) + (b))
 #define F_SUB(a, b) ((a) - (b))
 #define F_MUL(a, b) ((a) * (b))
@@ -163,6 +225,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, i
 #define F_ABS(a) ((a) < (T)0 ? -(a) : (a) == (T)0 ? (T)0 : (a))
 #define F_SQ(a) ((a) * (a))
 #define F_MOV(a) (a)
+#define F_FILL(a) (k)
     switch (I.op) {
       case VO_MOV: UN(F_MOV)
       case VO_NEG: UN(F_NEG)
@@ -180,7 +243,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, i
       case VO_MULI: UN(F_MULI)
       case VO_DIVI: UN(F_DIVI)
       case VO_RDIVI: UN(F_RDIVI)
-      case VO_FILL: { z0 = k; z1 = k; z2 = k; z3 = k; } break;
+      case VO_FILL: UN(F_FILL)
       case VO_RED:
       case VO_REDPROD: {
         // sequential over the slots in canonical order, valid slots only
@@ -191,21 +254,16 @@ __device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, i
           case 2: s = G.acc2; break;
           default: s = G.acc3; break;
         }
+        T p0 = x0, p1 = x1, p2 = x2, p3 = x3;
         if (I.op == VO_REDPROD) {
-          const T p0 = x0 * y0, p1 = x1 * y1, p2 = x2 * y2, p3 = x3 * y3;
-          {
-            if (vmask & 1) s = s + p0;
-            if (vmask & 2) s = s + p1;
-            if (vmask & 4) s = s + p2;
-            if (vmask & 8) s = s + p3;
-          }
-        } else {
-          {
-            if (vmask & 1) s = s + x0;
-            if (vmask & 2) s = s + x1;
-            if (vmask & 4) s = s + x2;
-            if (vmask & 8) s = s + x3;
-          }
+          p0 = x0 * y0; p1 = x1 * y1;
+          if constexpr (E == 4) { p2 = x2 * y2; p3 = x3 * y3; }
+        }
+        if (vmask & 1) s = s + p0;
+        if (vmask & 2) s = s + p1;
+        if constexpr (E == 4) {
+          if (vmask & 4) s = s + p2;
+          if (vmask & 8) s = s + p3;
         }
         switch (I.slot) {
           case 0: G.acc0 = s; break;
@@ -222,7 +280,14 @@ __device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, i
             case VO_EXP: UN(d_exp<T>)
             case VO_LOG: UN(d_log<T>)
             case VO_ERF: UN(d_erf<T>)
-            case VO_POW: BIN(d_pow<T>)
+            case VO_POW:
+              if constexpr (HV >= 2) {
+                z0 = d_pow<T>(x0, y0); z1 = d_pow<T>(x1, y1);
+                if constexpr (E == 4) { z2 = d_pow<T>(x2, y2); z3 = d_pow<T>(x3, y3); }
+              } else {
+                z0 = x0; z1 = x1; z2 = x2; z3 = x3;
+              }
+              break;
             default: { z0 = x0; z1 = x1; z2 = x2; z3 = x3; } break;
           }
         } else {
@@ -232,44 +297,55 @@ __device__ __forceinline__ void vm_step(const VmParams& P, DFX_RF, Regs<T>& G, i
     }
 #undef BIN
 #undef UN
-    G.z0 = z0; G.z1 = z1; G.z2 = z2; G.z3 = z3;
-    if (I.flags & VF_WB) { r0[d] = z0; r1[d] = z1; r2[d] = z2; r3[d] = z3; }
+    G.z0 = z0; G.z1 = z1;
+    if constexpr (E == 4) { G.z2 = z2; G.z3 = z3; }
+    if (I.flags & VF_WB) {
+      r0[d] = z0; r1[d] = z1;
+      if constexpr (E == 4) { r2[d] = z2; r3[d] = z3; }
+    }
   }
 
   // ---- stores -----------------------------------------------------------------
+  if (mode != MODE_SLOW) {
 #pragma unroll
-  for (int s = 0; s < VM_MAXOUT; ++s) {
-    if (s < P.n_out) {
-      const int o = P.out_reg[s];
-      T e[VM_E];
-      e[0] = r0[o]; e[1] = r1[o]; e[2] = r2[o]; e[3] = r3[o];
-      T* b = (T*)P.out[s].base;
-      const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;
-      if (FAST) {
+    for (int s = 0; s < VM_MAXOUT; ++s) {
+      if (s < P.n_out) {
+        const int o = P.out_reg[s];
+        T e[4];
+        e[0] = r0[o]; e[1] = r1[o];
+        if constexpr (E == 4) { e[2] = r2[o]; e[3] = r3[o]; }
+        T* b = (T*)P.out[s].base;
+        const int64_t sr = P.out[s].s_row;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           vecA w;
 #pragma unroll
           for (int v = 0; v < V; ++v) w[v] = e[u * V + v];
-          *(vecA*)(b + (row0 + u) * sr + c0) = w;
+          if (mode == MODE_FAST || ((vmask >> (u * V)) & 1)) *(vecA*)(b + (row0 + u) * sr + c0) = w;
         }
-      } else {
+      }
+    }
+  } else {
+    for (int s = 0; s < P.n_out; ++s) {
+      const int o = P.out_reg[s];
+      T e[4];
+      e[0] = r0[o]; e[1] = r1[o];
+      if constexpr (E == 4) { e[2] = r2[o]; e[3] = r3[o]; }
+      T* b = (T*)P.out[s].base;
+      const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-            if ((vmask >> (u * V + v)) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = e[u * V + v];
+      for (int q = 0; q < E; ++q) {
+        const int u = q / V, v = q % V;
+        if ((vmask >> q) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = e[q];
       }
     }
   }
 }
 
-template <typename T, bool HEAVY, int NINB, int NR>
+template <typename T, int HV, bool SPMV, int NINB>
 __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
-  constexpr int V = Lanes<T>::V, U = Lanes<T>::U, TW = Lanes<T>::TW;
-  static_assert(U * V == VM_E, "element slots");
-  // the planner never pairs a register file smaller than the stream bucket
-  if constexpr (NINB > NR) { return; } else {
+  typedef Shape<T, HV, SPMV> S;
+  constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, NR = S::NR;
 
   T r0[NR], r1[NR], r2[NR], r3[NR];
   Regs<T> G;
@@ -278,7 +354,8 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
     if (k < P.n_bc) {
       const T v = *(const T*)P.bc[k];
       const int r = P.bc_reg[k];
-      r0[r] = v; r1[r] = v; r2[r] = v; r3[r] = v;
+      r0[r] = v; r1[r] = v;
+      if constexpr (E == 4) { r2[r] = v; r3[r] = v; }
     }
   }
   G.z0 = G.z1 = G.z2 = G.z3 = (T)0;
@@ -304,20 +381,19 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
       if (row0 >= P.rows) break;
       const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
                                    : (row0 + U <= P.rows && cbase + TW <= P.cols);
-      const bool fast = P.unit_cols && interior;
-      unsigned vmask = (1u << VM_E) - 1;
-      if (!fast) {
+      int mode = MODE_FAST;
+      unsigned vmask = (1u << E) - 1;
+      if (!(P.unit_cols && interior)) {
+        mode = P.vec_cols ? MODE_CLAMP : MODE_SLOW;
         vmask = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const int64_t row = row0 + u, col = c0 + v;
-            const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col < P.cols);
-            vmask |= (ok ? 1u : 0u) << (u * V + v);
-          }
+        for (int e = 0; e < E; ++e) {
+          const int64_t row = row0 + e / V, col = c0 + e % V;
+          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col < P.cols);
+          vmask |= (ok ? 1u : 0u) << e;
+        }
       }
-      vm_step<T, HEAVY, NINB, NR>(P, r0, r1, r2, r3, G, row0, c0, vmask, fast);
+      vm_step<T, HV, SPMV, NINB>(P, r0, r1, r2, r3, G, row0, c0, vmask, mode);
     }
     // ---- tile partial sums ------------------------------------------------------
     if (P.n_red > 0) {
@@ -365,42 +441,56 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
     __threadfence();
     atomicExch(P.counter, 0u);
   }
-  }
 }
 
-#define DFX_INST(T, H, NR) \
-  template __global__ void vm_kernel<T, H, 2, NR>(const VmParams); \
-  template __global__ void vm_kernel<T, H, 4, NR>(const VmParams); \
-  template __global__ void vm_kernel<T, H, 6, NR>(const VmParams); \
-  template __global__ void vm_kernel<T, H, 10, NR>(const VmParams);
-DFX_INST(double, true, VM_NREG)
-DFX_INST(double, false, VM_NREG_LIGHT)
-DFX_INST(float, true, VM_NREG)
-DFX_INST(float, false, VM_NREG_LIGHT)
+#define DFX_INST(T, H, SP) \
+  template __global__ void vm_kernel<T, H, SP, 2>(const VmParams); \
+  template __global__ void vm_kernel<T, H, SP, 4>(const VmParams); \
+  template __global__ void vm_kernel<T, H, SP, 6>(const VmParams);
+DFX_INST(double, 0, false)
+DFX_INST(double, 0, true)
+DFX_INST(double, 1, false)
+DFX_INST(double, 1, true)
+DFX_INST(float, 0, false)
+DFX_INST(float, 0, true)
+DFX_INST(float, 1, false)
+DFX_INST(float, 1, true)
+// the widest stream bucket and pow exist only in the most general tier
+template __global__ void vm_kernel<double, 2, false, 10>(const VmParams);
+template __global__ void vm_kernel<double, 2, true, 10>(const VmParams);
+template __global__ void vm_kernel<float, 2, false, 10>(const VmParams);
+template __global__ void vm_kernel<float, 2, true, 10>(const VmParams);
 
-template <typename T, bool H, int NR>
+template <typename T, int H, bool SP>
 static void launch_t(const VmParams& P, int ninb, dim3 grid, hipStream_t st) {
-  switch (ninb) {
-    case 2: hipLaunchKernelGGL((vm_kernel<T, H, 2, NR>), grid, dim3(BLOCK), 0, st, P); break;
-    case 4: hipLaunchKernelGGL((vm_kernel<T, H, 4, NR>), grid, dim3(BLOCK), 0, st, P); break;
-    case 6: hipLaunchKernelGGL((vm_kernel<T, H, 6, NR>), grid, dim3(BLOCK), 0, st, P); break;
-    default: hipLaunchKernelGGL((vm_kernel<T, H, 10, NR>), grid, dim3(BLOCK), 0, st, P); break;
+  if constexpr (H == 2) {
+    hipLaunchKernelGGL((vm_kernel<T, 2, SP, 10>), grid, dim3(BLOCK), 0, st, P);
+  } else {
+    switch (ninb) {
+      case 2: hipLaunchKernelGGL((vm_kernel<T, H, SP, 2>), grid, dim3(BLOCK), 0, st, P); break;
+      case 4: hipLaunchKernelGGL((vm_kernel<T, H, SP, 4>), grid, dim3(BLOCK), 0, st, P); break;
+      default: hipLaunchKernelGGL((vm_kernel<T, H, SP, 6>), grid, dim3(BLOCK), 0, st, P); break;
+    }
   }
 }
 
-int stream_bucket(int n_in) { return n_in <= 2 ? 2 : n_in <= 4 ? 4 : n_in <= 6 ? 6 : 10; }
+int stream_bucket(int n_in, int tier) { return tier == 2 ? 10 : n_in <= 2 ? 2 : n_in <= 4 ? 4 : 6; }
 
-// Host-side launch; returns the hipError_t of the launch.
-int launch_vm(const VmParams& P, int is_f64, int heavy, hipStream_t stream) {
+// Host-side launch; returns the hipError_t of the launch.  `tier`: 0 arithmetic
+// only (8 registers), 1 with sqrt/exp/log/erf, 2 with pow (16 registers); tiers
+// 0 and 1 take at most 6 streams, tier 2 up to 10.
+int launch_vm(const VmParams& P, int is_f64, int tier, hipStream_t stream) {
   const dim3 grid(P.grid);
-  const int nb = stream_bucket(P.n_in);
+  const int nb = stream_bucket(P.n_in, tier);
+  if (P.n_in > nb) return (int)hipErrorInvalidValue;
+  const bool sp = P.spmv != 0;
+#define DFX_L(T, H) { if (sp) launch_t<T, H, true>(P, nb, grid, stream); else launch_t<T, H, false>(P, nb, grid, stream); }
   if (is_f64) {
-    if (heavy) launch_t<double, true, VM_NREG>(P, nb, grid, stream);
-    else launch_t<double, false, VM_NREG_LIGHT>(P, nb, grid, stream);
+    if (tier == 0) DFX_L(double, 0) else if (tier == 1) DFX_L(double, 1) else DFX_L(double, 2)
   } else {
-    if (heavy) launch_t<float, true, VM_NREG>(P, nb, grid, stream);
-    else launch_t<float, false, VM_NREG_LIGHT>(P, nb, grid, stream);
+    if (tier == 0) DFX_L(float, 0) else if (tier == 1) DFX_L(float, 1) else DFX_L(float, 2)
   }
+#undef DFX_L
   return (int)hipGetLastError();
 }
 

@@ -8,7 +8,6 @@ namespace dfx {
 
 constexpr int VM_NREG = 16;     // virtual registers per element slot (transcendental kernels)
 constexpr int VM_NREG_LIGHT = 8; // register file of the arithmetic-only kernels
-constexpr int VM_E = 4;         // element slots per lane per step
 constexpr int VM_MAXIN = 10;    // input streams
 constexpr int VM_MAXOUT = 6;    // output streams
 constexpr int VM_MAXBC = 8;     // broadcast 0-d inputs
@@ -28,7 +27,7 @@ constexpr int VM_MAXIMM = 24;   // immediates per pass
 constexpr int RED_TH = 32;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
-constexpr int FINAL_CHUNK = 2048;  // tree level width processed in LDS (power of two)
+constexpr int FINAL_CHUNK = 1024;  // tree level width processed in LDS (power of two)
 
 template <typename T> struct Lanes;
 template <> struct Lanes<double> { static constexpr int V = 2, U = 2, TW = WAVE * 2; };
@@ -67,6 +66,7 @@ struct VmParams {
   int32_t spmv;         // 1: row result of y = A x lands in VM_SPMV_REG first
   int32_t grid;         // blocks launched
   int32_t unit_cols;    // every stream has column stride 1 (padding slots 0)
+  int32_t vec_cols;     // unit_cols and the row width is a multiple of V
   int64_t rows, cols;   // 2-D space; for 1-D: rows = ceil(n1d / TW), cols = TW
   int64_t n1d;
   int64_t n_tiles, strips;  // tiles, tiles per tile-row
