@@ -22,8 +22,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-pthread"]
 # Device code: no packed FP32 instructions, IEEE-rounded fp32 divide/sqrt,
 # denormals kept.
+# Uniform (wave-wide) control flow, such as the op-list dispatch, is left
+# unstructured: structurising it adds flow blocks to every interpreted op.
 DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
-          "-fno-gpu-flush-denormals-to-zero",
+          "-fno-gpu-flush-denormals-to-zero", "-mllvm", "-structurizecfg-skip-uniform-regions=true",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 SOURCES = [

@@ -872,33 +872,31 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   out.code.clear();
   for (size_t i = 0; i < code.size(); ++i) {
     const SInstr& I = code[i];
-    VmInstr K{};
-    K.op = I.op;
-    K.imm = (uint16_t)I.imm;
-    K.slot = (uint8_t)I.slot;
+    unsigned flags = 0, ra = 0, rb = 0, rd = 0;
     const int prev = i > 0 ? code[i - 1].dst : -1;
     if (I.a >= 0) {
-      if (I.a == prev) K.flags |= VF_A_ACC;
-      else K.a = (uint8_t)vals[I.a].reg;
+      if (I.a == prev) flags |= VF_A_ACC;
+      else ra = (unsigned)vals[I.a].reg;
     }
     if (I.b >= 0) {
-      if (I.b == prev) K.flags |= VF_B_ACC;
-      else K.b = (uint8_t)vals[I.b].reg;
+      if (I.b == prev) flags |= VF_B_ACC;
+      else rb = (unsigned)vals[I.b].reg;
     }
     if (I.dst >= 0 && vals[I.dst].wb) {
-      K.flags |= VF_WB;
-      K.dst = (uint8_t)vals[I.dst].reg;
+      flags |= VF_WB;
+      rd = (unsigned)vals[I.dst].reg;
     }
+    VmInstr K = vm_instr(I.op, rd, ra, rb, flags, (unsigned)I.slot, (unsigned)I.imm);
     out.code.push_back(K);
   }
   for (auto& o : outs) {
     const auto key = written[o.second];
     const StoreRec& s = c.stores.at(L.order[key.first]);
     out.outs.push_back(make_stream(c, s, key.second, sp, tw, key.first));
-    out.out_reg.push_back((uint8_t)vals[o.first].reg);
+    out.out_reg.push_back(vals[o.first].reg);
   }
   for (size_t v = 0; v < vals.size(); ++v)
-    if (vals[v].kind == 1) out.bc_reg.push_back((uint8_t)vals[v].reg);
+    if (vals[v].kind == 1) out.bc_reg.push_back(vals[v].reg);
   out.unit_cols = 1;
   for (auto& s : out.ins) out.unit_cols &= s.s_col == 1;
   for (auto& s : out.outs) out.unit_cols &= s.s_col == 1;

@@ -95,9 +95,9 @@ struct PassPlan {
   int unit_cols = 1;
   std::vector<PStream> ins;
   std::vector<PStream> outs;
-  std::vector<uint8_t> out_reg;
+  std::vector<int32_t> out_reg;
   std::vector<int> bc_cstore;
-  std::vector<uint8_t> bc_reg;
+  std::vector<int32_t> bc_reg;
   std::vector<int> red_cstore;
   std::vector<int> red_init;
   int spmv_rowptr = -1, spmv_col = -1, spmv_val = -1, spmv_x = -1;

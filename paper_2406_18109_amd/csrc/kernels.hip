@@ -190,24 +190,26 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
 
   // ---- op list ----------------------------------------------------------------
   for (int pc = 0; pc < P.n_code; ++pc) {
-    const VmInstr I = P.code[pc];
-    const int d = I.dst, ia = I.a, ib = I.b;
+    const VmInstr I = P.code[pc];   // one scalar load; fields by shifts
+    const unsigned w0 = __builtin_amdgcn_readfirstlane(I.w0), w1 = __builtin_amdgcn_readfirstlane(I.w1);
+    const unsigned op = w0 & 0xff, flags = w1 & 0xff, slot = (w1 >> 8) & 0xff, immi = w1 >> 16;
+    const int d = (w0 >> 8) & 0xff, ia = (w0 >> 16) & 0xff, ib = w0 >> 24;
     T x0, x1, x2 = 0, x3 = 0, y0, y1, y2 = 0, y3 = 0;
-    if (I.flags & VF_A_ACC) {
+    if (flags & VF_A_ACC) {
       x0 = G.z0; x1 = G.z1;
       if constexpr (E == 4) { x2 = G.z2; x3 = G.z3; }
     } else {
       x0 = r0[ia]; x1 = r1[ia];
       if constexpr (E == 4) { x2 = r2[ia]; x3 = r3[ia]; }
     }
-    if (I.flags & VF_B_ACC) {
+    if (flags & VF_B_ACC) {
       y0 = G.z0; y1 = G.z1;
       if constexpr (E == 4) { y2 = G.z2; y3 = G.z3; }
     } else {
       y0 = r0[ib]; y1 = r1[ib];
       if constexpr (E == 4) { y2 = r2[ib]; y3 = r3[ib]; }
     }
-    const T k = (T)P.imm[I.imm];
+    const T k = (T)P.imm[immi];
     T z0, z1, z2 = 0, z3 = 0;
 #define BIN(EXPR) { z0 = EXPR(x0, y0); z1 = EXPR(x1, y1); if constexpr (E == 4) { z2 = EXPR(x2, y2); z3 = EXPR(x3, y3); } } break;
 #define UN(EXPR) { z0 = EXPR(x0); z1 = EXPR(x1); if constexpr (E == 4) { z2 = EXPR(x2); z3 = EXPR(x3); } } break;
@@ -226,7 +228,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
 #define F_SQ(a) ((a) * (a))
 #define F_MOV(a) (a)
 #define F_FILL(a) (k)
-    switch (I.op) {
+    switch (op) {
       case VO_MOV: UN(F_MOV)
       case VO_NEG: UN(F_NEG)
       case VO_ABS: UN(F_ABS)
@@ -248,14 +250,14 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
       case VO_REDPROD: {
         // sequential over the slots in canonical order, valid slots only
         T s;
-        switch (I.slot) {
+        switch (slot) {
           case 0: s = G.acc0; break;
           case 1: s = G.acc1; break;
           case 2: s = G.acc2; break;
           default: s = G.acc3; break;
         }
         T p0 = x0, p1 = x1, p2 = x2, p3 = x3;
-        if (I.op == VO_REDPROD) {
+        if (op == VO_REDPROD) {
           p0 = x0 * y0; p1 = x1 * y1;
           if constexpr (E == 4) { p2 = x2 * y2; p3 = x3 * y3; }
         }
@@ -265,7 +267,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
           if (vmask & 4) s = s + p2;
           if (vmask & 8) s = s + p3;
         }
-        switch (I.slot) {
+        switch (slot) {
           case 0: G.acc0 = s; break;
           case 1: G.acc1 = s; break;
           case 2: G.acc2 = s; break;
@@ -275,7 +277,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
       } break;
       default:
         if constexpr (HEAVY) {
-          switch (I.op) {
+          switch (op) {
             case VO_SQRT: UN(d_sqrt<T>)
             case VO_EXP: UN(d_exp<T>)
             case VO_LOG: UN(d_log<T>)
@@ -299,7 +301,7 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
 #undef UN
     G.z0 = z0; G.z1 = z1;
     if constexpr (E == 4) { G.z2 = z2; G.z3 = z3; }
-    if (I.flags & VF_WB) {
+    if (flags & VF_WB) {
       r0[d] = z0; r1[d] = z1;
       if constexpr (E == 4) { r2[d] = z2; r3[d] = z3; }
     }

@@ -49,11 +49,17 @@ enum VmFlag : uint8_t {
   VF_WB = 4       // write the result to register dst
 };
 
+// One instruction, two 32-bit words so the kernel fetches it with one scalar
+// load and decodes it with shifts:
+//   w0 = op | dst << 8 | a << 16 | b << 24
+//   w1 = flags | slot << 8 | imm << 16      (slot: reduction slot of RED/REDPROD)
 struct VmInstr {
-  uint8_t op, dst, a, b;
-  uint8_t flags, slot;  // slot: reduction slot for VO_RED / VO_REDPROD
-  uint16_t imm;         // immediate index
+  uint32_t w0, w1;
 };
+inline VmInstr vm_instr(unsigned op, unsigned dst, unsigned a, unsigned b, unsigned flags, unsigned slot,
+                        unsigned imm) {
+  return VmInstr{op | dst << 8 | a << 16 | b << 24, flags | slot << 8 | imm << 16};
+}
 
 struct VmStream {
   const void* base;     // address of the element at row 0, column 0
@@ -73,8 +79,8 @@ struct VmParams {
   int64_t tiles_per_wave;
   VmStream in[VM_MAXIN];
   VmStream out[VM_MAXOUT];
-  uint8_t out_reg[VM_MAXOUT];
-  uint8_t bc_reg[VM_MAXBC];
+  int32_t out_reg[VM_MAXOUT];
+  int32_t bc_reg[VM_MAXBC];
   const void* bc[VM_MAXBC];
   void* red_partials[VM_MAXRED];   // n_tiles entries each
   void* red_result[VM_MAXRED];     // 0-d store
