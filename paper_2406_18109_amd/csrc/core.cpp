@@ -901,8 +901,11 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   for (auto& s : out.ins) out.unit_cols &= s.s_col == 1;
   for (auto& s : out.outs) out.unit_cols &= s.s_col == 1;
   // launch shape: contiguous tile chunks per wave
+  // (a power of two, so that each block's tiles form an aligned subtree of
+  // the reduction tree)
   const int64_t target_waves = 8192;
-  out.tiles_per_wave = std::max<int64_t>(1, (out.n_tiles + target_waves - 1) / target_waves);
+  out.tiles_per_wave = 1;
+  while (out.tiles_per_wave < VM_MAXTPW && out.tiles_per_wave * target_waves < out.n_tiles) out.tiles_per_wave *= 2;
   const int64_t waves = (out.n_tiles + out.tiles_per_wave - 1) / out.tiles_per_wave;
   int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
   if (grid > 8) grid = (grid + 7) / 8 * 8;
@@ -924,7 +927,9 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     const StoreRec& rp = c.stores.at(L.order[out.spmv_rowptr]);
     const StoreRec& col = c.stores.at(L.order[out.spmv_col]);
     const StoreRec& x = c.stores.at(L.order[out.spmv_x]);
-    bytes += rp.elems * 4 + col.elems * (4 + (int64_t)es) + x.elems * (int64_t)es;
+    bytes += rp.elems * 4 + col.elems * (4 + (int64_t)es);
+    // the gathered vector is read once; it is often also a streamed operand
+    if (!rd.count(L.order[out.spmv_x])) bytes += x.elems * (int64_t)es;
   }
   out.alg_bytes = bytes;
   return DFX_OK;
@@ -979,11 +984,10 @@ static int ensure_workspace(Ctx& c, PassPlan& p) {
   if (c.analysis_only || p.red_cstore.empty() || p.ws) return DFX_OK;
   if (c.capturing) return fail(c, DFX_ESTATE, "a new fused window appeared while a graph is being recorded");
   const size_t es = dtype_size(p.dtype);
-  const size_t part = (size_t)std::max<int64_t>(1, p.n_tiles) * es;
-  p.ws_bytes = part * p.red_cstore.size() + 256;
+  const size_t part = ((size_t)p.grid * es + 255) / 256 * 256;  // one sum per block
+  p.ws_bytes = part * p.red_cstore.size();
   p.ws = dev_alloc(c, p.ws_bytes);
   if (!p.ws) return fail(c, DFX_ENOMEM, "workspace allocation failed");
-  HIPCHK(c, hipMemsetAsync(p.ws, 0, p.ws_bytes, c.stream));
   return DFX_OK;
 }
 
@@ -1049,22 +1053,29 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.bc[k] = S(p.bc_cstore[k]).ptr;
     P.bc_reg[k] = p.bc_reg[k];
   }
-  const size_t part = (size_t)std::max<int64_t>(1, p.n_tiles) * es;
+  const size_t part = ((size_t)p.grid * es + 255) / 256 * 256;
+  VmFinal F;
+  std::memset(&F, 0, sizeof(F));
+  F.n_red = P.n_red;
+  F.nblocks = (int32_t)((p.n_tiles + 4 * p.tiles_per_wave - 1) / (4 * p.tiles_per_wave));
   for (int k = 0; k < P.n_red; ++k) {
     P.red_partials[k] = (char*)p.ws + part * k;
-    P.red_result[k] = S(p.red_cstore[k]).ptr;
-    P.red_init[k] = p.red_init[k];
+    F.partials[k] = P.red_partials[k];
+    F.result[k] = S(p.red_cstore[k]).ptr;
+    F.init[k] = p.red_init[k];
   }
-  if (P.n_red) P.counter = (unsigned int*)((char*)p.ws + part * P.n_red);
   if (p.kind == 1) {
     P.rowptr = (const int32_t*)S(p.spmv_rowptr).ptr;
     P.colidx = (const int32_t*)S(p.spmv_col).ptr;
     P.val = S(p.spmv_val).ptr;
     P.x = S(p.spmv_x).ptr;
+    P.nnz = (int32_t)std::min<int64_t>(S(p.spmv_col).elems, S(p.spmv_val).elems);
+    P.nx = S(p.spmv_x).elems;
   }
   for (size_t i = 0; i < p.imm.size(); ++i) P.imm[i] = p.imm[i];
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);
+  if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
 }

@@ -15,6 +15,7 @@
 namespace dfx {
 
 int launch_vm(const VmParams& P, int is_f64, int tier, hipStream_t stream);
+int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream);
 int stream_bucket(int n_in, int tier);
 
 enum PartKind { PK_NONE = 0, PK_TILING = 1, PK_IMAGE = 2 };
@@ -104,7 +105,7 @@ struct PassPlan {
   std::vector<VmInstr> code;
   std::vector<double> imm;
   int64_t alg_bytes = 0;
-  // per-plan device workspace: reduction tile sums and the finish counter
+  // per-plan device workspace: one reduction subtree sum per block
   void* ws = nullptr;
   size_t ws_bytes = 0;
 };

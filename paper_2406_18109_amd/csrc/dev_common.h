@@ -30,30 +30,57 @@ template <typename T> __device__ void lds_tree(T* a, int L) {
 }
 
 
-// The pairwise power-of-two tree over a[0..L) (as lds_tree) computed by one
-// wave from global memory: aligned blocks of 64 leaves are complete subtrees,
-// so each is reduced with lane shuffles and the block sums are reduced the
-// same way.  L <= 64*64.  Every lane returns the total.
-__device__ __forceinline__ double wave_tree(const double* a, int L) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  double blk = 0.0;
-  const int nb = (L + WAVE - 1) / WAVE;
-  for (int c = 0; c < nb; ++c) {
-    const int Lb = min(WAVE, L - c * WAVE);
-    double v = lane < Lb ? __builtin_nontemporal_load(a + c * WAVE + lane) : 0.0;
-    for (int h = 1; h < Lb; h <<= 1) {
-      const double o = __shfl_down(v, h, WAVE);
-      if ((lane & (2 * h - 1)) == 0 && lane + h < Lb) v = v + o;
+// Row i of y = A x for a CSR matrix: summed sequentially in CSR order
+// (s = a0*x0, then s = s + ak*xk), nonzeros fetched eight at a time so that
+// several gathers are in flight.  Row pointers are clamped to [0, nnz] and
+// column indices to [0, nx): a malformed matrix yields wrong values, never an
+// access outside the arrays.
+template <typename T>
+__device__ __forceinline__ T csr_row(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                     const T* __restrict__ val, const T* __restrict__ x, int64_t i, int32_t nnz,
+                                     uint32_t nx) {
+  const int32_t rb = min(max(rowptr[i], 0), nnz);
+  const int32_t re = min(max(rowptr[i + 1], rb), nnz);
+  T s = (T)0;
+  for (int32_t k = rb; k < re; k += 8) {
+    int32_t c[8];
+    T a[8], xv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int32_t idx = k + j < re ? k + j : rb;
+      c[j] = colidx[idx];
+      a[j] = val[idx];
     }
-    const double s = __shfl(v, 0, WAVE);
-    if (lane == c) blk = s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xv[j] = x[(uint32_t)c[j] < nx ? c[j] : 0];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k + j < re) {
+        const T t = a[j] * xv[j];
+        s = (k + j == rb) ? t : s + t;
+      }
   }
-  double v = blk;
-  for (int h = 1; h < nb; h <<= 1) {
-    const double o = __shfl_down(v, h, WAVE);
-    if ((lane & (2 * h - 1)) == 0 && lane + h < nb) v = v + o;
+  return s;
+}
+
+// Move per-lane row results to the canonical owners: y[m] of lane l holds the
+// element 64m + l of a run of V*64 elements; lane l receives elements V*l + v
+// (v < V) in out[v].
+template <typename T, int V>
+__device__ __forceinline__ void rows_to_owners(const T (&y)[V], T (&out)[4]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int e = V * lane + v;
+    const int src = e & (WAVE - 1), sel = e / WAVE;
+    T r = (T)0;
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+      const T t = __shfl(y[m], src, WAVE);
+      r = sel == m ? t : r;
+    }
+    out[v] = r;
   }
-  return nb > 0 ? __shfl(v, 0, WAVE) : 0.0;
 }
 
 }  // namespace dfx

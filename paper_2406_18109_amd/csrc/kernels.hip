@@ -8,7 +8,8 @@
 // writes the output streams and accumulates reductions.  Temporaries of the
 // fused group never leave VGPRs.  Reductions follow the canonical tile tree
 // described in vm.h, so the result does not depend on which pass, fusion or
-// launch shape produced it; the last block to finish combines the tile sums.
+// launch shape produced it; each block reduces its aligned run of tile sums
+// in LDS and a one-block kernel launched after the pass combines the block sums.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -62,57 +63,21 @@ template <typename T, int HV, bool SPMV> struct Shape {
 
 enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
 
-// y = A x for the rows of the step's slots: each row is summed sequentially
-// in CSR order; four nonzeros of every slot are fetched per round so that
-// several gathers are in flight.
-template <typename T, int E, int U, int V, int TW>
-__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t row0, int64_t c0, unsigned vmask,
-                                          T (&out)[4]) {
-  const T* val = (const T*)P.val;
-  const T* x = (const T*)P.x;
-  int32_t rb[E], re[E];
+// y = A x for the V*64 elements of a step starting at element `base`.  The
+// row of element base + 64m + l is computed by lane l (consecutive rows on
+// consecutive lanes, so each load instruction touches few cache lines), then
+// handed to its owner in the canonical layout by shuffles.
+template <typename T, int V>
+__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&out)[4]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  T y[V];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int u = e / V, v = e % V;
-    const bool ok = (vmask >> e) & 1;
-    const int64_t i = ok ? (row0 + u) * TW + c0 + v : 0;
-    rb[e] = P.rowptr[i];
-    re[e] = ok ? P.rowptr[i + 1] : rb[e];
+  for (int m = 0; m < V; ++m) {
+    const int64_t i = base + m * WAVE + lane;
+    y[m] = i < P.n1d ? csr_row<T>(P.rowptr, P.colidx, (const T*)P.val, (const T*)P.x, i, P.nnz, (uint32_t)P.nx)
+                     : (T)0;
   }
-  int kmax = 0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) kmax = max(kmax, re[e] - rb[e]);
-  T s[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) s[e] = (T)0;
-  for (int k = 0; k < kmax; k += 4) {
-    int32_t cidx[E][4];
-    T a[E][4], xv[E][4];
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t idx = rb[e] + k + j;
-        const bool ok = idx < re[e];
-        cidx[e][j] = ok ? P.colidx[ok ? idx : 0] : 0;
-        a[e][j] = val[ok ? idx : 0];
-      }
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xv[e][j] = x[cidx[e][j]];
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (rb[e] + k + j < re[e]) {
-          const T t = a[e][j] * xv[e][j];
-          s[e] = (k + j == 0) ? t : s[e] + t;
-        }
-      }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) out[e] = s[e];
+  rows_to_owners<T, V>(y, out);
 }
 
 // One step: U rows of the tile, V columns per lane.
@@ -182,8 +147,9 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
     }
   }
   if constexpr (SPMV) {
+    static_assert(U == 1, "SpMV steps take one row of the tiling");
     T y[4];
-    spmv_rows<T, E, U, V, TW>(P, row0, c0, vmask, y);
+    spmv_rows<T, V>(P, row0 * TW, y);
     r0[NR - 1] = y[0]; r1[NR - 1] = y[1];
     if constexpr (E == 4) { r2[NR - 1] = y[2]; r3[NR - 1] = y[3]; }
   }
@@ -344,10 +310,13 @@ __device__ __forceinline__ void vm_step(const VmParams& P, T (&r0)[Shape<T, HV, 
   }
 }
 
+template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cnt, int lane);
+
 template <typename T, int HV, bool SPMV, int NINB>
 __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   typedef Shape<T, HV, SPMV> S;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, NR = S::NR;
+  __shared__ T tsum[VM_MAXRED][4 * VM_MAXTPW];  // this block's tile sums
 
   T r0[NR], r1[NR], r2[NR], r3[NR];
   Regs<T> G;
@@ -397,51 +366,82 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
       }
       vm_step<T, HV, SPMV, NINB>(P, r0, r1, r2, r3, G, row0, c0, vmask, mode);
     }
-    // ---- tile partial sums ------------------------------------------------------
+    // ---- tile sums into the block's LDS row ---------------------------------------
     if (P.n_red > 0) {
+      const int j = wib * (int)P.tiles_per_wave + (int)(t - t_begin);
       T a0 = wave_sum(G.acc0);
-      if (lane == 0) ((T*)P.red_partials[0])[t] = a0;
-      if (P.n_red > 1) { T a1 = wave_sum(G.acc1); if (lane == 0) ((T*)P.red_partials[1])[t] = a1; }
-      if (P.n_red > 2) { T a2 = wave_sum(G.acc2); if (lane == 0) ((T*)P.red_partials[2])[t] = a2; }
-      if (P.n_red > 3) { T a3 = wave_sum(G.acc3); if (lane == 0) ((T*)P.red_partials[3])[t] = a3; }
+      if (lane == 0) tsum[0][j] = a0;
+      if (P.n_red > 1) { T a1 = wave_sum(G.acc1); if (lane == 0) tsum[1][j] = a1; }
+      if (P.n_red > 2) { T a2 = wave_sum(G.acc2); if (lane == 0) tsum[2][j] = a2; }
+      if (P.n_red > 3) { T a3 = wave_sum(G.acc3); if (lane == 0) tsum[3][j] = a3; }
     }
   }
 
   if (P.n_red == 0) return;
-  // ---- last block combines the tile sums --------------------------------------
-  __shared__ T sh[FINAL_CHUNK];
-  __shared__ T sh2[FINAL_CHUNK];
-  __shared__ unsigned int ticket;
-  __threadfence();
+  // ---- block subtree: the 4 * tiles_per_wave tiles from lb * 4 * tiles_per_wave
+  // form one aligned subtree of the tile tree; wave k reduces reduction k.
   __syncthreads();
-  if (threadIdx.x == 0) ticket = atomicAdd(P.counter, 1u);
-  __syncthreads();
-  if (ticket != gridDim.x - 1) return;
-  __threadfence();
-  for (int k = 0; k < P.n_red; ++k) {
-    const T* part = (const T*)P.red_partials[k];
-    const int64_t n = P.n_tiles;
-    const int nch = (int)((n + FINAL_CHUNK - 1) / FINAL_CHUNK);
-    for (int c = 0; c < nch; ++c) {
-      const int64_t base = (int64_t)c * FINAL_CHUNK;
-      const int L = (int)min((int64_t)FINAL_CHUNK, n - base);
-      for (int i = threadIdx.x; i < L; i += BLOCK) sh[i] = __builtin_nontemporal_load(part + base + i);
-      __syncthreads();
-      lds_tree(sh, L);
-      if (threadIdx.x == 0) sh2[c] = sh[0];
+  if (wib >= P.n_red) return;
+  const int64_t blk0 = (int64_t)lb * 4 * P.tiles_per_wave;
+  if (blk0 >= P.n_tiles) return;
+  const int cnt = (int)min((int64_t)4 * P.tiles_per_wave, P.n_tiles - blk0);
+  const T v = block_tree(tsum[wib], cnt, lane);
+  if (lane == 0) ((T*)P.red_partials[wib])[lb] = v;
+}
+
+// Pairwise tree over a[0..cnt) (cnt <= 4 * WAVE) by one wave: lane l first
+// combines the aligned group a[4l..4l+4) -- a complete subtree when full --
+// then the group sums are combined across lanes level by level.  Every level
+// adds the right neighbour into the left one only when it exists, as in
+// lds_tree.  The result is valid in lane 0.
+template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cnt, int lane) {
+  const int j = 4 * lane;
+  T v = (T)0;
+  if (j < cnt) {
+    const int c = min(4, cnt - j);
+    const T v01 = c > 1 ? a[j] + a[j + 1] : a[j];
+    v = c == 4 ? v01 + (a[j + 2] + a[j + 3]) : c == 3 ? v01 + a[j + 2] : v01;
+  }
+  const int L = (cnt + 3) / 4;
+  for (int h = 1; h < L; h <<= 1) {
+    const T o = __shfl_down(v, h, WAVE);
+    if ((lane & (2 * h - 1)) == 0 && lane + h < L) v = v + o;
+  }
+  return v;
+}
+
+// Block sums -> 0-d results: chunks of FINAL_CHUNK block sums (complete
+// subtrees except the last) are reduced level by level in LDS, then the chunk
+// sums the same way.  All reductions of the pass advance together.
+template <typename T> __global__ __launch_bounds__(FINAL_BLOCK) void vm_final(const VmFinal F) {
+  __shared__ T sh[VM_MAXRED][FINAL_CHUNK];
+  __shared__ T cs[VM_MAXRED][FINAL_CHUNK];
+  const int tid = threadIdx.x;
+  const int nch = (F.nblocks + FINAL_CHUNK - 1) / FINAL_CHUNK;
+  for (int c = 0; c < nch; ++c) {
+    const int L = min(FINAL_CHUNK, F.nblocks - c * FINAL_CHUNK);
+    for (int k = 0; k < F.n_red; ++k)
+      sh[k][tid] = tid < L ? __builtin_nontemporal_load((const T*)F.partials[k] + (int64_t)c * FINAL_CHUNK + tid) : (T)0;
+    __syncthreads();
+    for (int h = 1; h < L; h <<= 1) {
+      const int i = tid * 2 * h;
+      if (i + h < L)
+        for (int k = 0; k < F.n_red; ++k) sh[k][i] = sh[k][i] + sh[k][i + h];
       __syncthreads();
     }
-    lds_tree(sh2, nch);
-    if (threadIdx.x == 0) {
-      const T total = nch > 0 ? sh2[0] : (T)0;
-      T* res = (T*)P.red_result[k];
-      *res = P.red_init[k] ? total : *res + total;
-    }
+    if (tid < F.n_red) cs[tid][c] = sh[tid][0];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    atomicExch(P.counter, 0u);
+  for (int h = 1; h < nch; h <<= 1) {
+    const int i = tid * 2 * h;
+    if (i + h < nch)
+      for (int k = 0; k < F.n_red; ++k) cs[k][i] = cs[k][i] + cs[k][i + h];
+    __syncthreads();
+  }
+  if (tid < F.n_red) {
+    const T total = nch > 0 ? cs[tid][0] : (T)0;
+    T* res = (T*)F.result[tid];
+    *res = F.init[tid] ? total : *res + total;
   }
 }
 
@@ -474,6 +474,15 @@ static void launch_t(const VmParams& P, int ninb, dim3 grid, hipStream_t st) {
       default: hipLaunchKernelGGL((vm_kernel<T, H, SP, 6>), grid, dim3(BLOCK), 0, st, P); break;
     }
   }
+}
+
+template __global__ void vm_final<double>(const VmFinal);
+template __global__ void vm_final<float>(const VmFinal);
+
+int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream) {
+  if (is_f64) hipLaunchKernelGGL(vm_final<double>, dim3(1), dim3(FINAL_BLOCK), 0, stream, F);
+  else hipLaunchKernelGGL(vm_final<float>, dim3(1), dim3(FINAL_BLOCK), 0, stream, F);
+  return (int)hipGetLastError();
 }
 
 int stream_bucket(int n_in, int tier) { return tier == 2 ? 10 : n_in <= 2 ? 2 : n_in <= 4 ? 4 : 6; }

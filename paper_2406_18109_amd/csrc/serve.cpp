@@ -109,6 +109,9 @@ struct Server {
   SolveDev* h_solves = nullptr;     // pinned mirror
   int32_t* d_items = nullptr;       // [slot list | tile list]
   int32_t* h_items = nullptr;       // pinned staging
+  int32_t* d_fin = nullptr;         // [new solves | all resident solves], max_slots each
+  int32_t* h_fin = nullptr;         // pinned staging
+  int n_fresh = 0, n_used = 0;
   size_t item_cap = 0;
   Tuner tuner;
   dfx_serve_counters stats{};
@@ -187,6 +190,7 @@ static bool admit_one(Server& S, ServeReq& q, int slot) {
 
 static int run_phase(Server& S, int phase, int64_t n_items, int64_t off) {
   if (n_items == 0) return 0;
+  const int max_slots = (int)S.slots.size();
   int trial = -1;
   const int ipw = S.tuner.pick(phase, n_items, &trial);
   ServeLaunch L;
@@ -196,6 +200,8 @@ static int run_phase(Server& S, int phase, int64_t n_items, int64_t off) {
   L.n_items = n_items;
   L.items_per_wave = ipw;
   L.phase = phase;
+  L.fin_slots = phase == PH_INIT ? S.d_fin : S.d_fin + max_slots;
+  L.n_fin = phase == PH_INIT ? S.n_fresh : S.n_used;
   const int64_t waves = (n_items + ipw - 1) / ipw;
   int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
   if (grid > 8) grid = (grid + 7) / 8 * 8;
@@ -256,9 +262,17 @@ static void scheduler(Server* Sp) {
     for (size_t i = 0; i < S.slots.size(); ++i)
       if (S.slots[i].used)
         for (int t = 0; t < S.slots[i].n_tiles; ++t) { S.h_items[k] = (int32_t)i; S.h_items[S.item_cap + k] = t; ++k; }
+    const size_t ms = S.slots.size();
+    S.n_fresh = S.n_used = 0;
+    for (size_t i = 0; i < ms; ++i) {
+      if (!S.slots[i].used) continue;
+      if (S.slots[i].fresh) S.h_fin[S.n_fresh++] = (int32_t)i;
+      S.h_fin[ms + S.n_used++] = (int32_t)i;
+    }
     bool ok = hipMemcpyAsync(S.d_items, S.h_items, k * sizeof(int32_t), hipMemcpyHostToDevice, S.stream) == hipSuccess &&
               hipMemcpyAsync(S.d_items + S.item_cap, S.h_items + S.item_cap, k * sizeof(int32_t),
-                             hipMemcpyHostToDevice, S.stream) == hipSuccess;
+                             hipMemcpyHostToDevice, S.stream) == hipSuccess &&
+              hipMemcpyAsync(S.d_fin, S.h_fin, 2 * ms * sizeof(int32_t), hipMemcpyHostToDevice, S.stream) == hipSuccess;
     int e = ok ? 0 : 1;
     if (!e) e = run_phase(S, PH_INIT, (int64_t)n_new, 0);
     if (!e) e = run_phase(S, PH_SPMV_DOT, (int64_t)n_all, (int64_t)n_new);
@@ -326,8 +340,21 @@ int dfx_serve_start(dfx_ctx* c, const dfx_serve_cfg* cfg) {
             hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc((void**)&S->d_solves, sizeof(SolveDev) * cfg->max_slots) == hipSuccess &&
             hipHostMalloc((void**)&S->h_solves, sizeof(SolveDev) * cfg->max_slots, hipHostMallocDefault) == hipSuccess &&
+            hipMalloc((void**)&S->d_fin, sizeof(int32_t) * 2 * cfg->max_slots) == hipSuccess &&
+            hipHostMalloc((void**)&S->h_fin, sizeof(int32_t) * 2 * cfg->max_slots, hipHostMallocDefault) == hipSuccess &&
             hipEventCreate(&S->ev0) == hipSuccess && hipEventCreate(&S->ev1) == hipSuccess;
-  if (!ok) { c->err = "serving set-up failed"; delete S; return DFX_EHIP; }
+  if (!ok) {
+    if (S->d_solves) (void)hipFree(S->d_solves);
+    if (S->h_solves) (void)hipHostFree(S->h_solves);
+    if (S->d_fin) (void)hipFree(S->d_fin);
+    if (S->h_fin) (void)hipHostFree(S->h_fin);
+    if (S->ev0) (void)hipEventDestroy(S->ev0);
+    if (S->ev1) (void)hipEventDestroy(S->ev1);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    c->err = "serving set-up failed";
+    return DFX_EHIP;
+  }
   std::memset(S->h_solves, 0, sizeof(SolveDev) * cfg->max_slots);
   c->server = S;
   S->th = std::thread(scheduler, S);
@@ -345,7 +372,7 @@ int dfx_serve_submit(dfx_ctx* c, const dfx_csr_desc* A, const double* b, uint64_
     if (A->rowptr[i + 1] < A->rowptr[i]) { c->err = "rowptr must be non-decreasing"; return DFX_EINVAL; }
   for (int64_t k = 0; k < A->nnz; ++k)
     if (A->col[k] < 0 || A->col[k] >= A->n) { c->err = "column index out of range"; return DFX_EINVAL; }
-  if (tiles_of(A->n) > 64 * 64) { c->err = "solve too large for the batched executor"; return DFX_EUNSUPPORTED; }
+  if (tiles_of(A->n) > S_MAXTILES) { c->err = "solve too large for the batched executor"; return DFX_EUNSUPPORTED; }
   const size_t fp = footprint_of(A->n, A->nnz);
   std::lock_guard<std::mutex> lk(S->mu);
   if (!S->err.empty()) { c->err = S->err; return DFX_EHIP; }
@@ -459,6 +486,8 @@ int dfx_serve_stop(dfx_ctx* c) {
   if (S->h_items) (void)hipHostFree(S->h_items);
   (void)hipFree(S->d_solves);
   (void)hipHostFree(S->h_solves);
+  if (S->d_fin) (void)hipFree(S->d_fin);
+  if (S->h_fin) (void)hipHostFree(S->h_fin);
   (void)hipEventDestroy(S->ev0);
   (void)hipEventDestroy(S->ev1);
   (void)hipStreamDestroy(S->stream);

@@ -24,9 +24,9 @@ struct SolveDev {
   double rho, pq, alpha, beta, bnorm;
   int32_t iters;
   int32_t status;       // SOLVE_* below
-  unsigned int counter; // tiles finished in the current phase
-  int32_t pad;
 };
+
+constexpr int S_MAXTILES = 64 * 64;  // tiles per solve (the tile tree fits one block's LDS)
 
 enum SolveStatus {
   SOLVE_INIT = 0,       // admitted, r = b and rho not yet formed
@@ -47,6 +47,8 @@ struct ServeLaunch {
   int64_t items_per_wave;
   int32_t phase;
   int32_t grid;
+  const int32_t* fin_slots;  // the solves of this phase, one block each in the scalar update
+  int32_t n_fin;
 };
 
 }  // namespace dfx

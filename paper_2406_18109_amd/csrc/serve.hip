@@ -4,9 +4,9 @@
 // canonical order of the op-list kernel (lane l owns columns 2l, 2l+1 of each
 // 128-element row; 32 rows per tile), so the tile sums -- and, through the
 // same pairwise tree, every dot product -- are identical whatever else is in
-// the batch.  The last wave to finish a solve's tiles in a phase (device-scope
-// ticket) forms that solve's scalars: rho and ||b|| (init), alpha = rho/(p.q),
-// or beta = rho'/rho and the convergence test.
+// the batch.  A second launch, one block per solve of the phase, reduces the
+// solve's tile sums and forms its scalars: rho and ||b|| (init),
+// alpha = rho/(p.q), or beta = rho'/rho and the convergence test.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -17,30 +17,6 @@ namespace dfx {
 
 constexpr int S_TW = 128;   // FP64 row width of the canonical tiling
 constexpr int S_TH = RED_TH;
-
-__device__ __forceinline__ double csr_row(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                          const double* __restrict__ val, const double* __restrict__ x,
-                                          int64_t i) {
-  const int32_t b = rowptr[i], e = rowptr[i + 1];
-  double s = 0.0;
-  int32_t k = b;
-  // four nonzeros per round keep several gathers in flight; the sum is
-  // still sequential in CSR order
-  for (; k + 4 <= e; k += 4) {
-    const int32_t c0 = col[k], c1 = col[k + 1], c2 = col[k + 2], c3 = col[k + 3];
-    const double a0 = val[k], a1 = val[k + 1], a2 = val[k + 2], a3 = val[k + 3];
-    const double t0 = a0 * x[c0], t1 = a1 * x[c1], t2 = a2 * x[c2], t3 = a3 * x[c3];
-    s = (k == b) ? t0 : s + t0;
-    s = s + t1;
-    s = s + t2;
-    s = s + t3;
-  }
-  for (; k < e; ++k) {
-    const double t = val[k] * x[col[k]];
-    s = (k == b) ? t : s + t;
-  }
-  return s;
-}
 
 __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -65,7 +41,32 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
     double* __restrict__ q = S->q;
     const double alpha = S->alpha, beta = S->beta;
     double acc = 0.0;
-    for (int rr = 0; rr < S_TH; ++rr) {
+    if (phase == PH_SPMV_DOT) {
+      // q = A p with consecutive rows on consecutive lanes, then p.q in the
+      // canonical order (lane l owns elements 2l, 2l+1 of each row)
+      const int32_t nnz = S->rowptr[n];
+      for (int rr = 0; rr < S_TH; ++rr) {
+        const int64_t sb = ((int64_t)tile * S_TH + rr) * S_TW;
+        if (sb >= n) break;
+        double y[2], qo[4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int64_t i = sb + m * WAVE + lane;
+          y[m] = i < n ? csr_row<double>(S->rowptr, S->col, S->val, p, i, nnz, (uint32_t)n) : 0.0;
+          if (i < n) q[i] = y[m];
+        }
+        rows_to_owners<double, 2>(y, qo);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int64_t i = sb + 2 * lane + v;
+          if (i < n) {
+            const double t = p[i] * qo[v];
+            acc = acc + t;
+          }
+        }
+      }
+    }
+    for (int rr = 0; rr < S_TH && phase != PH_SPMV_DOT; ++rr) {
       const int64_t base = ((int64_t)tile * S_TH + rr) * S_TW + 2 * lane;
       if (base - 2 * lane >= n) break;
 #pragma unroll
@@ -79,12 +80,6 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
             p[i] = bi;
             x[i] = 0.0;
             const double t = bi * bi;
-            acc = acc + t;
-          } break;
-          case PH_SPMV_DOT: {
-            const double qi = csr_row(S->rowptr, S->col, S->val, p, i);
-            q[i] = qi;
-            const double t = p[i] * qi;
             acc = acc + t;
           } break;
           case PH_AXPY_DOT: {
@@ -106,40 +101,45 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
     if (phase == PH_UPDATE_P) continue;
     const double ts = wave_sum(acc);
     if (lane == 0) S->partials[tile] = ts;
-    __threadfence();
-    unsigned int ticket = 0;
-    if (lane == 0) ticket = atomicAdd(&S->counter, 1u);
-    ticket = __shfl(ticket, 0, WAVE);
-    if (ticket != (unsigned int)S->n_tiles - 1) continue;
-    // last tile of this solve in this phase: form its scalars
-    __threadfence();
-    const double total = wave_tree(S->partials, S->n_tiles);
-    if (lane == 0) {
-      if (phase == PH_INIT) {
-        S->rho = total;
-        S->bnorm = sqrt(total);
-        S->status = !isfinite(total) ? SOLVE_BREAKDOWN : (total == 0.0 ? SOLVE_CONVERGED : SOLVE_RUN);
-      } else if (phase == PH_SPMV_DOT) {
-        S->pq = total;
-        if (!(total > 0.0) || !isfinite(total)) S->status = SOLVE_BREAKDOWN;
-        else S->alpha = S->rho / total;
-      } else {
-        const double rho_new = total;
-        S->beta = rho_new / S->rho;
-        S->rho = rho_new;
-        S->iters = S->iters + 1;
-        if (!isfinite(rho_new)) S->status = SOLVE_BREAKDOWN;
-        else if (sqrt(rho_new) <= S->tol * S->bnorm) S->status = SOLVE_CONVERGED;
-        else if (S->iters >= S->max_iter) S->status = SOLVE_MAXITER;
-      }
-      __threadfence();
-      atomicExch(&S->counter, 0u);
-    }
+  }
+}
+
+// One block per listed solve: the pairwise tree over its tile sums (as the
+// op-list executor's tile tree), then the phase's scalar update.
+__global__ __launch_bounds__(BLOCK) void serve_final_kernel(SolveDev* solves, const int32_t* slots, int phase) {
+  __shared__ double sh[S_MAXTILES];
+  SolveDev* S = solves + slots[blockIdx.x];
+  const int status = S->status;
+  if (phase == PH_INIT ? status != SOLVE_INIT : status != SOLVE_RUN) return;
+  const int L = S->n_tiles;
+  for (int i = threadIdx.x; i < L; i += BLOCK) sh[i] = __builtin_nontemporal_load(S->partials + i);
+  __syncthreads();
+  lds_tree(sh, L);
+  if (threadIdx.x != 0) return;
+  const double total = L > 0 ? sh[0] : 0.0;
+  if (phase == PH_INIT) {
+    S->rho = total;
+    S->bnorm = sqrt(total);
+    S->status = !isfinite(total) ? SOLVE_BREAKDOWN : (total == 0.0 ? SOLVE_CONVERGED : SOLVE_RUN);
+  } else if (phase == PH_SPMV_DOT) {
+    S->pq = total;
+    if (!(total > 0.0) || !isfinite(total)) S->status = SOLVE_BREAKDOWN;
+    else S->alpha = S->rho / total;
+  } else {
+    const double rho_new = total;
+    S->beta = rho_new / S->rho;
+    S->rho = rho_new;
+    S->iters = S->iters + 1;
+    if (!isfinite(rho_new)) S->status = SOLVE_BREAKDOWN;
+    else if (sqrt(rho_new) <= S->tol * S->bnorm) S->status = SOLVE_CONVERGED;
+    else if (S->iters >= S->max_iter) S->status = SOLVE_MAXITER;
   }
 }
 
 int launch_serve_phase(const ServeLaunch& L, hipStream_t stream) {
   hipLaunchKernelGGL(serve_phase_kernel, dim3(L.grid), dim3(BLOCK), 0, stream, L);
+  if (L.phase != PH_UPDATE_P && L.n_fin > 0)
+    hipLaunchKernelGGL(serve_final_kernel, dim3(L.n_fin), dim3(BLOCK), 0, stream, L.solves, L.fin_slots, L.phase);
   return (int)hipGetLastError();
 }
 

@@ -24,10 +24,19 @@ constexpr int VM_MAXIMM = 24;   // immediates per pass
 // lane sums are combined by an xor butterfly (32, 16, 8, 4, 2, 1), and the
 // tile sums by a pairwise power-of-two tree over the tile index.  V = 16
 // bytes / element size.  Nothing here depends on the launch configuration.
+//
+// Evaluation of the tile tree: a wave owns a power-of-two run of at most
+// VM_MAXTPW tiles starting at a multiple of the run length, so the 4 runs of
+// a block form one aligned subtree, which the block reduces in LDS; a
+// one-block kernel launched after the pass reduces the block sums (subtrees
+// of equal size) with the same tree.  Kernel boundaries order the two, so no
+// device-scope fence is needed inside the pass.
 constexpr int RED_TH = 32;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
+constexpr int VM_MAXTPW = 64;      // tiles per wave (power of two)
 constexpr int FINAL_CHUNK = 1024;  // tree level width processed in LDS (power of two)
+constexpr int FINAL_BLOCK = 1024;  // threads of the block-sum kernel (= FINAL_CHUNK)
 
 template <typename T> struct Lanes;
 template <> struct Lanes<double> { static constexpr int V = 2, U = 2, TW = WAVE * 2; };
@@ -76,22 +85,30 @@ struct VmParams {
   int64_t rows, cols;   // 2-D space; for 1-D: rows = ceil(n1d / TW), cols = TW
   int64_t n1d;
   int64_t n_tiles, strips;  // tiles, tiles per tile-row
-  int64_t tiles_per_wave;
+  int64_t tiles_per_wave;  // power of two, at most VM_MAXTPW
   VmStream in[VM_MAXIN];
   VmStream out[VM_MAXOUT];
   int32_t out_reg[VM_MAXOUT];
   int32_t bc_reg[VM_MAXBC];
   const void* bc[VM_MAXBC];
-  void* red_partials[VM_MAXRED];   // n_tiles entries each
-  void* red_result[VM_MAXRED];     // 0-d store
-  int32_t red_init[VM_MAXRED];
-  unsigned int* counter;           // blocks finished (reset by the last block)
-  const int32_t* rowptr;           // SpMV operands
+  void* red_partials[VM_MAXRED];   // one subtree sum per block
+  const int32_t* rowptr;           // SpMV operands (n1d + 1 row pointers)
   const int32_t* colidx;
   const void* val;
   const void* x;
+  int32_t nnz;                     // length of colidx and val
+  int64_t nx;                      // length of x
   double imm[VM_MAXIMM];
   VmInstr code[VM_MAXCODE];
+};
+
+// The block-sum kernel: reduces `nblocks` block sums per reduction and stores
+// (init) or accumulates into the 0-d result.
+struct VmFinal {
+  int32_t n_red, nblocks;
+  const void* partials[VM_MAXRED];
+  void* result[VM_MAXRED];
+  int32_t init[VM_MAXRED];
 };
 
 }  // namespace dfx
