@@ -32,6 +32,10 @@ SOURCES = [
     ("core.cpp", False),
     ("serve.cpp", False),
     ("kernels.hip", True),
+    ("vm_tier0.hip", True),
+    ("vm_tier1.hip", True),
+    ("vm_tier2.hip", True),
+    ("vm_tier3.hip", True),
     ("serve.hip", True),
 ]
 

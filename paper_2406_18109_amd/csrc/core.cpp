@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -639,6 +640,16 @@ static Box stream_box(Ctx& c, const StoreRec& s, int part, const Space& sp) {
   return b;
 }
 
+// DFX_TRACE=1 prints one line per lowered pass to stderr, DFX_TRACE=2 also
+// its instructions.
+static int trace_level() {
+  static const int lvl = [] {
+    const char* e = std::getenv("DFX_TRACE");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lvl;
+}
+
 static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& tasks, const Space& sp,
                       int dtype, int kind, PassPlan& out) {
   const int tw = dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW;
@@ -810,7 +821,7 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   // unused inputs are still loaded (their stream is bound); unused
   // broadcasts are dropped from the register file but keep their slot
   if (out.ins.size() > (size_t)VM_MAXIN || out.bc_cstore.size() > (size_t)VM_MAXBC ||
-      code.size() > (size_t)VM_MAXCODE || out.imm.size() > (size_t)VM_MAXIMM ||
+      code.size() > (size_t)VM_MAXCODE ||
       outs.size() > (size_t)VM_MAXOUT)
     return fail(c, DFX_EUNSUPPORTED, "fused pass exceeds the kernel's stream/op limits");
 
@@ -863,11 +874,16 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   };
   const int nin = (int)out.ins.size();
   bool ok = false;
-  if (!has_pow && !heavy && nin <= 6) { tier = 0; ok = allocate(VM_NREG_LIGHT, stream_bucket(nin, 0)); }
-  if (!ok && !has_pow && nin <= 6) { tier = 1; ok = allocate(VM_NREG, stream_bucket(nin, 1)); }
-  if (!ok) { tier = 2; ok = allocate(VM_NREG, stream_bucket(nin, 2)); }
+  if (!has_pow && nin <= 6) {
+    tier = heavy ? TIER_TRANS8 : TIER_ARITH;
+    ok = allocate(VM_NREG_LIGHT, stream_bucket(nin, tier));
+    if (!ok) { tier = TIER_TRANS16; ok = allocate(VM_NREG, stream_bucket(nin, tier)); }
+  }
+  if (!ok) { tier = TIER_POW; ok = allocate(VM_NREG, stream_bucket(nin, tier)); }
   if (!ok) return fail(c, DFX_EUNSUPPORTED, "fused pass needs more than 16 live values");
   out.tier = tier;
+  out.nreg = 0;
+  for (auto& v : vals) out.nreg = std::max(out.nreg, v.reg + 1);
   // emit kernel instructions with operand forwarding
   out.code.clear();
   for (size_t i = 0; i < code.size(); ++i) {
@@ -886,7 +902,8 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
       flags |= VF_WB;
       rd = (unsigned)vals[I.dst].reg;
     }
-    VmInstr K = vm_instr(I.op, rd, ra, rb, flags, (unsigned)I.slot, (unsigned)I.imm);
+    const double immv = I.imm >= 0 && I.imm < (int)out.imm.size() ? out.imm[I.imm] : 0.0;
+    VmInstr K = vm_instr(I.op, rd, ra, rb, flags, (unsigned)I.slot, immv, dtype == DFX_F64);
     out.code.push_back(K);
   }
   for (auto& o : outs) {
@@ -932,6 +949,19 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     if (!rd.count(L.order[out.spmv_x])) bytes += x.elems * (int64_t)es;
   }
   out.alg_bytes = bytes;
+  if (trace_level() > 0) {
+    std::fprintf(stderr,
+                 "dfx: pass kind=%d %s tier=%d regs=%d code=%zu in=%zu out=%zu bc=%zu red=%zu tiles=%lld "
+                 "tiles/wave=%lld grid=%d alg_bytes=%lld\n",
+                 kind, dtype == DFX_F64 ? "f64" : "f32", out.tier, out.nreg, out.code.size(), out.ins.size(),
+                 out.outs.size(), out.bc_cstore.size(), out.red_cstore.size(), (long long)out.n_tiles,
+                 (long long)out.tiles_per_wave, out.grid, (long long)out.alg_bytes);
+    if (trace_level() > 1)
+      for (auto& K : out.code)
+        std::fprintf(stderr, "dfx:   op=%u flags=%u slot=%u dst=%u a=%u b=%u imm=%08x%08x\n", K.w0 & 0xff,
+                     (K.w0 >> 8) & 0xff, (K.w0 >> 16) & 0xff, K.w1 & 0xff, (K.w1 >> 8) & 0xff,
+                     (K.w1 >> 16) & 0xff, K.w3, K.w2);
+  }
   return DFX_OK;
 }
 
@@ -1072,7 +1102,6 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.nnz = (int32_t)std::min<int64_t>(S(p.spmv_col).elems, S(p.spmv_val).elems);
     P.nx = S(p.spmv_x).elems;
   }
-  for (size_t i = 0; i < p.imm.size(); ++i) P.imm[i] = p.imm[i];
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);
   if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);

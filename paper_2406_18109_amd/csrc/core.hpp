@@ -92,6 +92,7 @@ struct PassPlan {
   int64_t rows = 1, cols = 1, n1d = 1;
   int64_t n_tiles = 0, strips = 1, tiles_per_wave = 1;
   int grid = 1;
+  int nreg = 0;          // registers the allocation uses
   int tier = 0;          // kernel tier: 0 arithmetic, 1 transcendental, 2 with pow
   int unit_cols = 1;
   std::vector<PStream> ins;

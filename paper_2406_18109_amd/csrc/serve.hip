@@ -22,7 +22,7 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
   const int lane = threadIdx.x & (WAVE - 1);
   int lb = blockIdx.x;
   if ((L.grid & 7) == 0) lb = (blockIdx.x & 7) * (L.grid >> 3) + (blockIdx.x >> 3);
-  const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + threadIdx.x / WAVE;
+  const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t i0 = gw * L.items_per_wave;
   const int64_t i1 = min(i0 + L.items_per_wave, L.n_items);
   const int phase = L.phase;

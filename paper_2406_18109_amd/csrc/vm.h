@@ -6,14 +6,13 @@
 
 namespace dfx {
 
-constexpr int VM_NREG = 16;     // virtual registers per element slot (transcendental kernels)
-constexpr int VM_NREG_LIGHT = 8; // register file of the arithmetic-only kernels
+constexpr int VM_NREG = 16;      // virtual registers per element slot, large register file
+constexpr int VM_NREG_LIGHT = 8; // small register file
 constexpr int VM_MAXIN = 10;    // input streams
 constexpr int VM_MAXOUT = 6;    // output streams
 constexpr int VM_MAXBC = 8;     // broadcast 0-d inputs
 constexpr int VM_MAXRED = 4;    // reductions per pass
 constexpr int VM_MAXCODE = 112; // instructions per pass
-constexpr int VM_MAXIMM = 24;   // immediates per pass
 // The SpMV row result lands in the last register of the file (NR - 1).
 
 // Canonical reduction tiling.  The iteration space is a set of rows of at
@@ -39,8 +38,8 @@ constexpr int FINAL_CHUNK = 1024;  // tree level width processed in LDS (power o
 constexpr int FINAL_BLOCK = 1024;  // threads of the block-sum kernel (= FINAL_CHUNK)
 
 template <typename T> struct Lanes;
-template <> struct Lanes<double> { static constexpr int V = 2, U = 2, TW = WAVE * 2; };
-template <> struct Lanes<float> { static constexpr int V = 4, U = 1, TW = WAVE * 4; };
+template <> struct Lanes<double> { static constexpr int V = 2, TW = WAVE * 2; };
+template <> struct Lanes<float> { static constexpr int V = 4, TW = WAVE * 4; };
 
 enum VmOp : uint8_t {
   VO_MOV = 0, VO_NEG, VO_ABS, VO_SQUARE, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_MAX, VO_MIN,
@@ -58,17 +57,36 @@ enum VmFlag : uint8_t {
   VF_WB = 4       // write the result to register dst
 };
 
-// One instruction, two 32-bit words so the kernel fetches it with one scalar
-// load and decodes it with shifts:
-//   w0 = op | dst << 8 | a << 16 | b << 24
-//   w1 = flags | slot << 8 | imm << 16      (slot: reduction slot of RED/REDPROD)
+// One instruction, four 32-bit words fetched with one scalar load:
+//   w0 = op | flags << 8 | slot << 16     (slot: reduction slot of RED/REDPROD)
+//   w1 = dst | a << 8 | b << 16           (register indices, extracted by bit-field)
+//   w2, w3 = the immediate in the pass's element type (FP32: w2 only)
 struct VmInstr {
-  uint32_t w0, w1;
+  uint32_t w0, w1, w2, w3;
 };
 inline VmInstr vm_instr(unsigned op, unsigned dst, unsigned a, unsigned b, unsigned flags, unsigned slot,
-                        unsigned imm) {
-  return VmInstr{op | dst << 8 | a << 16 | b << 24, flags | slot << 8 | imm << 16};
+                        double imm, bool f64) {
+  VmInstr I{op | flags << 8 | slot << 16, dst | a << 8 | b << 16, 0, 0};
+  if (f64) {
+    uint64_t u;
+    __builtin_memcpy(&u, &imm, 8);
+    I.w2 = (uint32_t)u;
+    I.w3 = (uint32_t)(u >> 32);
+  } else {
+    const float f = (float)imm;
+    __builtin_memcpy(&I.w2, &f, 4);
+  }
+  return I;
 }
+
+// Kernel tiers: register file size and op set.  Tiers 0-2 take up to 6 input
+// streams; tier 3 takes up to VM_MAXIN.
+enum VmTier {
+  TIER_ARITH = 0,   // arithmetic ops, 8 registers
+  TIER_TRANS8 = 1,  // plus sqrt/exp/log/erf, 8 registers
+  TIER_TRANS16 = 2, // plus sqrt/exp/log/erf, 16 registers
+  TIER_POW = 3      // every op, 16 registers, up to VM_MAXIN streams
+};
 
 struct VmStream {
   const void* base;     // address of the element at row 0, column 0
@@ -98,8 +116,7 @@ struct VmParams {
   const void* x;
   int32_t nnz;                     // length of colidx and val
   int64_t nx;                      // length of x
-  double imm[VM_MAXIMM];
-  VmInstr code[VM_MAXCODE];
+  VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
 
 // The block-sum kernel: reduces `nblocks` block sums per reduction and stores

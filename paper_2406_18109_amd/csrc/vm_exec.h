@@ -1,0 +1,476 @@
+// HIP executor for gfx950: the op-list kernel that runs one fused pass.
+//
+// A pass is a fused group of tasks over one iteration space (section 4.2's
+// fused task; its body is the tasks' bodies composed in program order).  Each
+// lane holds E element slots; for every step the kernel loads the input
+// streams into virtual registers, interprets the op list over the slots with
+// wave-uniform register indices (scalar-branch dispatch, indexed VGPR moves),
+// writes the output streams and accumulates reductions.  Temporaries of the
+// fused group never leave VGPRs.  Reductions follow the canonical tile tree
+// described in vm.h, so the result does not depend on which pass, fusion or
+// launch shape produced it; each block reduces its aligned run of tile sums
+// in LDS and a one-block kernel launched after the pass combines the block
+// sums.  The kernel templates are instantiated per tier in their own sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dev_common.h"
+#include "vm.h"
+
+namespace dfx {
+
+template <typename T> __device__ __forceinline__ T d_sqrt(T x);
+template <> __device__ __forceinline__ double d_sqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float d_sqrt<float>(float x) { return sqrtf(x); }
+template <typename T> __device__ __forceinline__ T d_exp(T x);
+template <> __device__ __forceinline__ double d_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float d_exp<float>(float x) { return expf(x); }
+template <typename T> __device__ __forceinline__ T d_log(T x);
+template <> __device__ __forceinline__ double d_log<double>(double x) { return log(x); }
+template <> __device__ __forceinline__ float d_log<float>(float x) { return logf(x); }
+template <typename T> __device__ __forceinline__ T d_erf(T x);
+template <> __device__ __forceinline__ double d_erf<double>(double x) { return erf(x); }
+template <> __device__ __forceinline__ float d_erf<float>(float x) { return erff(x); }
+template <typename T> __device__ __forceinline__ T d_pow(T x, T y);
+template <> __device__ __forceinline__ double d_pow<double>(double x, double y) { return pow(x, y); }
+template <> __device__ __forceinline__ float d_pow<float>(float x, float y) { return powf(x, y); }
+
+template <typename T> __device__ __forceinline__ T d_max(T x, T y) { return (x > y || x != x) ? x : y; }
+template <typename T> __device__ __forceinline__ T d_min(T x, T y) { return (x < y || x != x) ? x : y; }
+template <typename T> __device__ __forceinline__ T d_abs(T x) { return x < (T)0 ? -x : x == (T)0 ? (T)0 : x; }
+
+#ifndef DFX_TRANS8_F64_ROWS
+#define DFX_TRANS8_F64_ROWS 2
+#endif
+#ifndef DFX_ARITH_F64_GS
+#define DFX_ARITH_F64_GS 1
+#endif
+
+template <typename T, int HV, bool SPMV, int NR_> struct Shape {
+  static constexpr bool HEAVY = HV > 0;
+  static constexpr int V = Lanes<T>::V;
+  static constexpr int TW = Lanes<T>::TW;
+  static constexpr int NR = NR_;
+  // Rows per step: two where the register file of NR registers x E elements
+  // stays within 64 VGPRs, else one; SpMV steps take one row.  Rows are
+  // visited in order either way, so the canonical reduction order does not
+  // depend on U.
+  static constexpr int FIT = 256 / (NR * V * (int)sizeof(T));
+  static constexpr int U = SPMV ? 1
+                         : (HEAVY && NR == VM_NREG_LIGHT && sizeof(T) == 8) ? DFX_TRANS8_F64_ROWS
+                         : (FIT >= 2 ? 2 : 1);
+  static constexpr int E = U * V;
+  // The register file is split into NG arrays of NR vectors of GS elements.
+  // An array of at most 128 bytes (32 VGPRs) is the largest that indexed VGPR
+  // moves reach without falling back to scratch; fetching an operand for
+  // every slot takes NG indexed blocks.  Transcendental and FP32 kernels use
+  // the widest groups (fewest blocks per interpreted op); the FP64
+  // arithmetic kernels keep one array per slot, which measured faster for
+  // their stream-bound passes.
+  static constexpr int GS_MAX = 128 / NR / (int)sizeof(T) < E ? 128 / NR / (int)sizeof(T) : E;
+  static constexpr int GS = (!HEAVY && sizeof(T) == 8) ? DFX_ARITH_F64_GS : GS_MAX;
+  static constexpr int NG = E / GS;
+  static_assert(GS >= 1 && GS <= GS_MAX && NG * GS == E && NG <= 4, "register file split");
+};
+
+// GS elements of one register group (a scalar when GS == 1).  The groups are
+// separate arrays (R0..R3) so each stays its own allocation; FOR_G
+// expands a statement for each group with `g` and `Rg` bound at compile time.
+#define FOR_G(...)                          \
+  {                                         \
+    {                                       \
+      constexpr int g = 0;                  \
+      auto& Rg = R0;                        \
+      (void)g; (void)Rg;                    \
+      __VA_ARGS__                           \
+    }                                       \
+    if constexpr (NG > 1) {                 \
+      constexpr int g = 1;                  \
+      auto& Rg = R1;                        \
+      (void)g; (void)Rg;                    \
+      __VA_ARGS__                           \
+    }                                       \
+    if constexpr (NG > 2) {                 \
+      constexpr int g = 2;                  \
+      auto& Rg = R2;                        \
+      (void)g; (void)Rg;                    \
+      __VA_ARGS__                           \
+    }                                       \
+    if constexpr (NG > 3) {                 \
+      constexpr int g = 3;                  \
+      auto& Rg = R3;                        \
+      (void)g; (void)Rg;                    \
+      __VA_ARGS__                           \
+    }                                       \
+  }
+template <typename T, int GS> struct GVec { typedef T type __attribute__((ext_vector_type(GS))); };
+template <typename T> struct GVec<T, 1> { typedef T type; };
+
+template <typename T, int GS> __device__ __forceinline__ T gget(const typename GVec<T, GS>::type& v, int c) {
+  if constexpr (GS == 1) return v;
+  else return v[c];
+}
+template <typename T, int GS> __device__ __forceinline__ void gset(typename GVec<T, GS>::type& v, int c, T x) {
+  if constexpr (GS == 1) v = x;
+  else v[c] = x;
+}
+
+template <typename T, int NG, int GS> struct VmState {
+  typedef typename GVec<T, GS>::type gvec;
+  gvec z[NG];               // previous instruction's result (forwarded operand)
+  T acc0, acc1, acc2, acc3; // this lane's reduction accumulators
+};
+
+enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
+
+// y = A x for the V*64 elements of a step starting at element `base`.  The
+// row of element base + 64m + l is computed by lane l (consecutive rows on
+// consecutive lanes, so each load instruction touches few cache lines), then
+// handed to its owner in the canonical layout by shuffles.
+template <typename T, int V>
+__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&out)[4]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  T y[V];
+#pragma unroll
+  for (int m = 0; m < V; ++m) {
+    const int64_t i = base + m * WAVE + lane;
+    y[m] = i < P.n1d ? csr_row<T>(P.rowptr, P.colidx, (const T*)P.val, (const T*)P.x, i, P.nnz, (uint32_t)P.nx)
+                     : (T)0;
+  }
+  rows_to_owners<T, V>(y, out);
+}
+
+// One step: U rows of the tile, V columns per lane.
+//   MODE_FAST : every slot of every lane valid, unit column strides: vector
+//               loads of all streams issued back to back.
+//   MODE_CLAMP: validity is whole V-vectors (unit strides, widths multiple
+//               of V): the same vector loads with invalid lanes pointed at
+//               the stream's first element and zeroed.
+//   MODE_SLOW : per-element masked accesses, one stream at a time.
+// Slots n_in..NINB-1 of the bucket read a 4 KB zero page in the vector modes.
+template <typename T, int HV, bool SPMV, int NR, int NINB>
+__device__ __forceinline__ void vm_step(
+    const VmParams& P,
+    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R0)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R1)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R2)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R3)[NR],
+    VmState<T, Shape<T, HV, SPMV, NR>::NG, Shape<T, HV, SPMV, NR>::GS>& G, int64_t row0, int64_t c0,
+    unsigned vmask, const int mode) {
+  typedef Shape<T, HV, SPMV, NR> S;
+  constexpr bool HEAVY = S::HEAVY;
+  constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
+  static_assert(NINB <= NR, "stream bucket exceeds the register file");
+  typedef typename GVec<T, GS>::type gvec;
+  typedef T vecA __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  // element e of a register lives in group e / GS, component e % GS
+#define RSET(a, e, x) { const int g_ = (e) / GS; \
+    if (g_ == 0) gset<T, GS>(R0[a], (e) % GS, x); else if (g_ == 1) gset<T, GS>(R1[a], (e) % GS, x); \
+    else if (g_ == 2) gset<T, GS>(R2[a], (e) % GS, x); else gset<T, GS>(R3[a], (e) % GS, x); }
+
+  // ---- loads: every load of the step in flight before the first wait --------
+  if (mode != MODE_SLOW) {
+    T L[NINB][E];
+    bool okv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      const T* b = (const T*)P.in[a].base;
+      // column stride is 1 for real streams and 0 for padding slots
+      const int64_t cc = c0 & (-P.in[a].s_col);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const T* p = b + (row0 + u) * P.in[a].s_row + cc;
+        if (mode == MODE_CLAMP) p = okv[u] ? p : b;
+        const vecA w = *(const vecA*)p;
+#pragma unroll
+        for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
+      }
+    }
+    if (mode == MODE_CLAMP) {
+#pragma unroll
+      for (int a = 0; a < NINB; ++a)
+#pragma unroll
+        for (int e = 0; e < E; ++e) L[a][e] = ((vmask >> e) & 1) ? L[a][e] : (T)0;
+    }
+#pragma unroll
+    for (int a = 0; a < NINB; ++a)
+#pragma unroll
+      for (int e = 0; e < E; ++e) RSET(a, e, L[a][e]);
+  } else {
+    for (int a = 0; a < P.n_in; ++a) {
+      const T* b = (const T*)P.in[a].base;
+      const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;
+      gvec w[NG];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int u = e / V, v = e % V;
+        const bool ok = (vmask >> e) & 1;
+        const T q = b[ok ? (row0 + u) * sr + (c0 + v) * sc : 0];
+        gset<T, GS>(w[e / GS], e % GS, ok ? q : (T)0);
+      }
+      FOR_G(Rg[a] = w[g];)
+    }
+  }
+  if constexpr (SPMV) {
+    static_assert(U == 1, "SpMV steps take one row of the tiling");
+    T y[4];
+    spmv_rows<T, V>(P, row0 * TW, y);
+#pragma unroll
+    for (int e = 0; e < E; ++e) RSET(NR - 1, e, y[e]);
+  }
+
+  // ---- op list: the next instruction's load overlaps the current op --------
+  VmInstr nx = P.code[0];
+  for (int pc = 0; pc < P.n_code; ++pc) {
+    const unsigned w0 = __builtin_amdgcn_readfirstlane(nx.w0), w1 = __builtin_amdgcn_readfirstlane(nx.w1);
+    const unsigned w2 = __builtin_amdgcn_readfirstlane(nx.w2), w3 = __builtin_amdgcn_readfirstlane(nx.w3);
+    nx = P.code[pc + 1];
+    const unsigned op = w0 & 0xff, flags = (w0 >> 8) & 0xff, slot = (w0 >> 16) & 0xff;
+    const unsigned d = w1 & 0xff, ia = (w1 >> 8) & 0xff, ib = (w1 >> 16) & 0xff;
+    T k;
+    if constexpr (sizeof(T) == 8) k = __builtin_bit_cast(double, ((uint64_t)w3 << 32) | w2);
+    else k = __builtin_bit_cast(float, w2);
+    gvec x[NG], y[NG], z[NG];
+    if (flags & VF_A_ACC) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) x[g] = G.z[g];
+    } else {
+      FOR_G(x[g] = Rg[ia];)
+    }
+    if (flags & VF_B_ACC) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) y[g] = G.z[g];
+    } else {
+      FOR_G(y[g] = Rg[ib];)
+    }
+#define VEC(EXPR) { _Pragma("unroll") for (int g = 0; g < NG; ++g) z[g] = EXPR; } break;
+#define UN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(z[e / GS], e % GS, F(gget<T, GS>(x[e / GS], e % GS))); } break;
+#define BIN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(z[e / GS], e % GS, F(gget<T, GS>(x[e / GS], e % GS), gget<T, GS>(y[e / GS], e % GS))); } break;
+    switch (op) {
+      case VO_MOV: VEC(x[g])
+      case VO_NEG: VEC(-x[g])
+      case VO_ABS: UN(d_abs<T>)
+      case VO_SQUARE: VEC(x[g] * x[g])
+      case VO_ADD: VEC(x[g] + y[g])
+      case VO_SUB: VEC(x[g] - y[g])
+      case VO_MUL: VEC(x[g] * y[g])
+      case VO_DIV: VEC(x[g] / y[g])
+      case VO_MAX: BIN(d_max<T>)
+      case VO_MIN: BIN(d_min<T>)
+      case VO_ADDI: VEC(x[g] + k)
+      case VO_SUBI: VEC(x[g] - k)
+      case VO_RSUBI: VEC(k - x[g])
+      case VO_MULI: VEC(x[g] * k)
+      case VO_DIVI: VEC(x[g] / k)
+      case VO_RDIVI: VEC(k / x[g])
+      case VO_FILL: VEC((gvec)k)
+      case VO_RED:
+      case VO_REDPROD: {
+        // sequential over the slots in canonical order, valid slots only
+        T s = slot == 0 ? G.acc0 : slot == 1 ? G.acc1 : slot == 2 ? G.acc2 : G.acc3;
+        gvec pr[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) pr[g] = op == VO_REDPROD ? x[g] * y[g] : x[g];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if ((vmask >> e) & 1) s = s + gget<T, GS>(pr[e / GS], e % GS);
+        switch (slot) {
+          case 0: G.acc0 = s; break;
+          case 1: G.acc1 = s; break;
+          case 2: G.acc2 = s; break;
+          default: G.acc3 = s; break;
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) z[g] = x[g];
+      } break;
+      default:
+#pragma unroll
+        for (int g = 0; g < NG; ++g) z[g] = x[g];
+        if constexpr (HEAVY) {
+          switch (op) {
+            case VO_SQRT: UN(d_sqrt<T>)
+            case VO_EXP: UN(d_exp<T>)
+            case VO_LOG: UN(d_log<T>)
+            case VO_ERF: UN(d_erf<T>)
+            case VO_POW:
+              if constexpr (HV >= 2) {
+                BIN(d_pow<T>)
+              }
+              break;
+            default: break;
+          }
+        }
+        break;
+    }
+#undef VEC
+#undef BIN
+#undef UN
+#pragma unroll
+    for (int g = 0; g < NG; ++g) G.z[g] = z[g];
+    if (flags & VF_WB) FOR_G(Rg[d] = z[g];)
+  }
+
+  // ---- stores -----------------------------------------------------------------
+  if (mode != MODE_SLOW) {
+#pragma unroll
+    for (int s = 0; s < VM_MAXOUT; ++s) {
+      if (s < P.n_out) {
+        const int o = P.out_reg[s];
+        gvec ev[NG];
+        FOR_G(ev[g] = Rg[o];)
+        T* b = (T*)P.out[s].base;
+        const int64_t sr = P.out[s].s_row;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          vecA w;
+#pragma unroll
+          for (int v = 0; v < V; ++v) w[v] = gget<T, GS>(ev[(u * V + v) / GS], (u * V + v) % GS);
+          if (mode == MODE_FAST) *(vecA*)(b + (row0 + u) * sr + c0) = w;
+          else if ((vmask >> (u * V)) & 1) *(vecA*)(b + (row0 + u) * sr + c0) = w;
+        }
+      }
+    }
+  } else {
+    for (int s = 0; s < P.n_out; ++s) {
+      const int o = P.out_reg[s];
+      gvec ev[NG];
+      FOR_G(ev[g] = Rg[o];)
+      T* b = (T*)P.out[s].base;
+      const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int u = q / V, v = q % V;
+        if ((vmask >> q) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = gget<T, GS>(ev[q / GS], q % GS);
+      }
+    }
+  }
+#undef RSET
+}
+
+// Pairwise tree over a[0..cnt) (cnt <= 4 * WAVE) by one wave: lane l first
+// combines the aligned group a[4l..4l+4) -- a complete subtree when full --
+// then the group sums are combined across lanes level by level.  Every level
+// adds the right neighbour into the left one only when it exists, as in
+// lds_tree.  The result is valid in lane 0.
+template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cnt, int lane) {
+  const int j = 4 * lane;
+  T v = (T)0;
+  if (j < cnt) {
+    const int c = min(4, cnt - j);
+    const T v01 = c > 1 ? a[j] + a[j + 1] : a[j];
+    v = c == 4 ? v01 + (a[j + 2] + a[j + 3]) : c == 3 ? v01 + a[j + 2] : v01;
+  }
+  const int L = (cnt + 3) / 4;
+  for (int h = 1; h < L; h <<= 1) {
+    const T o = __shfl_down(v, h, WAVE);
+    if ((lane & (2 * h - 1)) == 0 && lane + h < L) v = v + o;
+  }
+  return v;
+}
+
+template <typename T, int HV, bool SPMV, int NR, int NINB>
+__global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
+  typedef Shape<T, HV, SPMV, NR> S;
+  constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
+  typedef typename GVec<T, GS>::type gvec;
+  __shared__ T tsum[VM_MAXRED][4 * VM_MAXTPW];  // this block's tile sums
+
+  gvec R0[NR], R1[NR], R2[NR], R3[NR];  // groups beyond NG are unused (and dropped)
+  VmState<T, NG, GS> G;
+#pragma unroll
+  for (int k = 0; k < VM_MAXBC; ++k) {
+    if (k < P.n_bc) {
+      const gvec v = (gvec)(*(const T*)P.bc[k]);
+      const int r = P.bc_reg[k];
+      FOR_G(Rg[r] = v;)
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) G.z[g] = (gvec)(T)0;
+
+  const int lane = threadIdx.x & (WAVE - 1);
+  // wave-uniform by construction; readfirstlane lets the compiler keep the
+  // tile and row bookkeeping (and the step-mode branches) in scalar registers
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  // XCD-aware numbering: consecutive blocks land on different XCDs, so give
+  // each XCD a contiguous range of logical blocks (and therefore of tiles).
+  int lb = blockIdx.x;
+  if ((P.grid & 7) == 0) lb = (blockIdx.x & 7) * (P.grid >> 3) + (blockIdx.x >> 3);
+  const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + wib;
+  const int64_t t_begin = gw * P.tiles_per_wave;
+  const int64_t t_end = min(t_begin + P.tiles_per_wave, P.n_tiles);
+
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int64_t tr = t / P.strips;
+    const int64_t ts = t - tr * P.strips;
+    const int64_t cbase = ts * TW;
+    const int64_t c0 = cbase + (int64_t)lane * V;
+    G.acc0 = G.acc1 = G.acc2 = G.acc3 = (T)0;
+    for (int r = 0; r < RED_TH; r += U) {
+      const int64_t row0 = tr * RED_TH + r;
+      if (row0 >= P.rows) break;
+      const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
+                                   : (row0 + U <= P.rows && cbase + TW <= P.cols);
+      int mode = MODE_FAST;
+      unsigned vmask = (1u << E) - 1;
+      if (!(P.unit_cols && interior)) {
+        mode = P.vec_cols ? MODE_CLAMP : MODE_SLOW;
+        vmask = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int64_t row = row0 + e / V, col = c0 + e % V;
+          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col < P.cols);
+          vmask |= (ok ? 1u : 0u) << e;
+        }
+      }
+      vm_step<T, HV, SPMV, NR, NINB>(P, R0, R1, R2, R3, G, row0, c0, vmask, mode);
+    }
+    // ---- tile sums into the block's LDS row ---------------------------------------
+    if (P.n_red > 0) {
+      const int j = wib * (int)P.tiles_per_wave + (int)(t - t_begin);
+      T a0 = wave_sum(G.acc0);
+      if (lane == 0) tsum[0][j] = a0;
+      if (P.n_red > 1) { T a1 = wave_sum(G.acc1); if (lane == 0) tsum[1][j] = a1; }
+      if (P.n_red > 2) { T a2 = wave_sum(G.acc2); if (lane == 0) tsum[2][j] = a2; }
+      if (P.n_red > 3) { T a3 = wave_sum(G.acc3); if (lane == 0) tsum[3][j] = a3; }
+    }
+  }
+
+  if (P.n_red == 0) return;
+  // ---- block subtree: the 4 * tiles_per_wave tiles from lb * 4 * tiles_per_wave
+  // form one aligned subtree of the tile tree; wave k reduces reduction k.
+  __syncthreads();
+  if (wib >= P.n_red) return;
+  const int64_t blk0 = (int64_t)lb * 4 * P.tiles_per_wave;
+  if (blk0 >= P.n_tiles) return;
+  const int cnt = (int)min((int64_t)4 * P.tiles_per_wave, P.n_tiles - blk0);
+  const T v = block_tree(tsum[wib], cnt, lane);
+  if (lane == 0) ((T*)P.red_partials[wib])[lb] = v;
+}
+
+// Launch one pass on a tier's kernels: element type, SpMV prologue and
+// stream bucket select the instantiation.
+template <int HV, int NR, int NB0, int NB1, int NB2>
+int launch_tier(const VmParams& P, int is_f64, int nb, hipStream_t st) {
+  const dim3 g(P.grid), b(BLOCK);
+  const bool sp = P.spmv != 0;
+#define DFX_L(T, SP)                                                                              \
+  {                                                                                               \
+    if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0>), g, b, 0, st, P);           \
+    else if (nb == NB1) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB1>), g, b, 0, st, P);      \
+    else hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB2>), g, b, 0, st, P);                     \
+  }
+  if (is_f64) {
+    if (sp) DFX_L(double, true) else DFX_L(double, false)
+  } else {
+    if (sp) DFX_L(float, true) else DFX_L(float, false)
+  }
+#undef DFX_L
+  return (int)hipGetLastError();
+}
+
+}  // namespace dfx
