@@ -9,7 +9,8 @@ group executed as one kernel.  Inputs are resident in HBM before timing.
 Printed: one JSON line with the headline (fused algorithmic HBM GB/s), the
 roofline of the dominant kernel, the CPU oracle timed on a bounded sample,
 and the other legs of the metric (unfused GB/s, FP32, Jacobi stencil, CG
-iterations/s) under "legs".  Progress goes to stderr.
+iterations/s, and the continuous-batching server's solves/s with p50/p99
+latency over the 4096-request stream) under "legs".  Progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -30,7 +31,10 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("paper_2406_18109_amd/csrc/kernels.hip", "paper_2406_18109_amd/csrc/vm.h"):
+    for f in ("paper_2406_18109_amd/csrc/kernels.hip", "paper_2406_18109_amd/csrc/vm.h",
+              "paper_2406_18109_amd/csrc/vm_exec.h", "paper_2406_18109_amd/csrc/dev_common.h",
+              "paper_2406_18109_amd/csrc/vm_tier0.hip", "paper_2406_18109_amd/csrc/vm_tier1.hip",
+              "paper_2406_18109_amd/csrc/vm_tier2.hip", "paper_2406_18109_amd/csrc/vm_tier3.hip"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -178,6 +182,74 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
     return out
 
 
+def serve_leg(dfx, synth, np, count, rate, budget, slots):
+    """Continuous-batching server on the first `count` requests of the serving
+    stream: 2-D Poisson solves, side uniform in [32, 512], tol 1e-8, Poisson
+    arrivals at `rate` per second.  Latency = completion - arrival."""
+    import threading
+    sides = synth.serve_sides(count)
+    arrivals = synth.serve_arrivals(count, rate)
+    mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
+    c = dfx.Context(device=0)
+    c.serve_start(hbm_budget=budget, max_slots=slots, tol=1e-8, max_iter=20000)
+    tickets = [None] * count
+
+    def feeder():
+        t0 = time.perf_counter()
+        for i in range(count):
+            side = int(sides[i])
+            b = synth.serve_rhs(i, side * side)
+            d = arrivals[i] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            rp, col, val = mats[side]
+            tickets[i] = c.serve_submit(rp, col, val, b)
+
+    t_start = time.perf_counter()
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    res = []
+    for i, t in enumerate(tickets):
+        res.append(c.serve_wait(t, 3600))
+        c.serve_release(t)
+        if i % 256 == 255 or i == count - 1:
+            log("serve: %d of %d requests done" % (i + 1, count))
+    wall = time.perf_counter() - t_start
+    st = c.serve_stats()
+    c.serve_stop()
+    c.close()
+    lat = np.array([r["t_done"] - r["t_arrive"] for r in res])
+    its = np.array([r["iterations"] for r in res])
+    ok = sum(1 for r in res if r["status"] == 2)
+    return {"requests": count, "converged": ok, "arrival_rate_per_s": rate, "solves_per_s": count / wall,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_iterations": float(its.mean()), "rounds": st["rounds"], "launches": st["launches"],
+            "peak_bytes": st["peak_bytes"], "hbm_budget": budget, "max_slots": slots, "wall_s": wall}
+
+
+def copy_leg(dfx, np, torch, n, K):
+    """One COPY task over n doubles per step (reads and writes 8n bytes each):
+    the streaming reference, and the known-size kernel that calibrates the
+    HBM traffic counters."""
+    c = dfx.Context(device=0, window_size=4)
+    a = c.store_create([n], "f64")
+    c.store_write(a, np.zeros(n))
+    b = c.store_create([n], "f64")
+    T = c.part_tiling([n])
+
+    def step():
+        c.submit("copy", [1], [(a, T, "R"), (b, T, "W")])
+        c.flush()
+    for _ in range(2):
+        step()
+    wall, ev = timed_steps(torch, c.torch_stream, step, K)
+    c.close()
+    ev_ms = sum(ev) / len(ev)
+    return {"elements": n, "ms_per_step": wall, "event_ms_per_step": ev_ms,
+            "gbs": 16.0 * n / (ev_ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(synth, wl, np, sample):
     S, K, T = synth.bs_inputs(sample)
     r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL)
@@ -198,7 +270,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="all", help="all | headline")
+    ap.add_argument("--legs", default="all", help="all | headline | serve | copy")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-rate", type=float, default=120.0)
     ap.add_argument("--log2n", type=int, default=26)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -215,6 +289,13 @@ def main():
 
     n = 1 << args.log2n
     K, W = args.steps, args.warmup
+    if args.legs == "copy":
+        print(json.dumps(copy_leg(dfx, np, torch, n, K)))
+        return
+    if args.legs == "serve":
+        out = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
+        print(json.dumps(out))
+        return
     log("black-scholes f64 fused n=2^%d" % args.log2n)
     fused = bs_leg(torch, dfx, synth, wl, np, n, "f64", True, K, W)
     log("fused", fused)
@@ -235,6 +316,8 @@ def main():
         log("cg 256^3")
         legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
+        log("serving: %d CG solves, Poisson arrivals at %.0f/s" % (args.serve_requests, args.serve_rate))
+        legs["serve"] = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
         for a, b in (("bs_f64_fused", "bs_f64_unfused"), ("bs_f32_fused", "bs_f32_unfused")):
             legs[a]["speedup_vs_unfused"] = legs[b]["ms_per_step"] / legs[a]["ms_per_step"]
         legs["jacobi_fused"]["speedup_vs_unfused"] = legs["jacobi_unfused"]["ms_per_sweep"] / legs["jacobi_fused"]["ms_per_sweep"]
