@@ -278,9 +278,8 @@ static void scheduler(Server* Sp) {
     if (!e) e = run_phase(S, PH_SPMV_DOT, (int64_t)n_all, (int64_t)n_new);
     if (!e) e = run_phase(S, PH_AXPY_DOT, (int64_t)n_all, (int64_t)n_new);
     if (!e) e = run_phase(S, PH_UPDATE_P, (int64_t)n_all, (int64_t)n_new);
-    for (size_t i = 0; i < S.slots.size(); ++i)
-      if (S.slots[i].used && !e)
-        e = hipMemcpyAsync(S.h_solves + i, S.d_solves + i, sizeof(SolveDev), hipMemcpyDeviceToHost, S.stream);
+    // one transfer of every slot's state (unused slots are ignored below)
+    if (!e) e = hipMemcpyAsync(S.h_solves, S.d_solves, sizeof(SolveDev) * S.slots.size(), hipMemcpyDeviceToHost, S.stream);
     if (!e) e = hipStreamSynchronize(S.stream);
     if (e) { std::lock_guard<std::mutex> lk(S.mu); fail_locked(S, "round failed: " + std::string(hipGetErrorString((hipError_t)e))); break; }
     S.stats.rounds += 1;

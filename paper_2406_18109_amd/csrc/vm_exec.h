@@ -142,6 +142,38 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
   rows_to_owners<T, V>(y, out);
 }
 
+// Vector-mode loads of one step (MODE_FAST or MODE_CLAMP) into L: every
+// stream's loads issued back to back before the first wait.  Padding slots
+// of the stream bucket are not loaded: their registers are free registers of
+// the pass, written before they are read.
+template <typename T, int V, int U, int E, int NINB>
+__device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int64_t row0, int64_t c0, unsigned vmask,
+                                        const int mode) {
+  typedef T vecA __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  bool okv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
+#pragma unroll
+  for (int a = 0; a < NINB; ++a) {
+    if (a >= P.n_in) break;
+    const T* b = (const T*)P.in[a].base;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T* p = b + (row0 + u) * P.in[a].s_row + c0;
+      if (mode == MODE_CLAMP) p = okv[u] ? p : b;
+      const vecA w = *(const vecA*)p;
+#pragma unroll
+      for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
+    }
+  }
+  if (mode == MODE_CLAMP) {
+#pragma unroll
+    for (int a = 0; a < NINB; ++a)
+#pragma unroll
+      for (int e = 0; e < E; ++e) L[a][e] = ((vmask >> e) & 1) ? L[a][e] : (T)0;
+  }
+}
+
 // One step: U rows of the tile, V columns per lane.
 //   MODE_FAST : every slot of every lane valid, unit column strides: vector
 //               loads of all streams issued back to back.
@@ -150,15 +182,21 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
 //               the stream's first element and zeroed.
 //   MODE_SLOW : per-element masked accesses, one stream at a time.
 // Slots n_in..NINB-1 of the bucket read a 4 KB zero page in the vector modes.
-template <typename T, int HV, bool SPMV, int NR, int NINB>
+// With SPLIT the caller has instead issued the step's loads into L (see
+// vm_load), and with `pf_next` (software-pipelined kernels) the loads of the next
+// step (row next_row0, known to be MODE_FAST) are issued into L as soon as
+// this step's values are in registers, so they are in flight during the op
+// list and the stores.
+template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT>
 __device__ __forceinline__ void vm_step(
     const VmParams& P,
     typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R0)[NR],
     typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R1)[NR],
     typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R2)[NR],
     typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R3)[NR],
-    VmState<T, Shape<T, HV, SPMV, NR>::NG, Shape<T, HV, SPMV, NR>::GS>& G, int64_t row0, int64_t c0,
-    unsigned vmask, const int mode) {
+    VmState<T, Shape<T, HV, SPMV, NR>::NG, Shape<T, HV, SPMV, NR>::GS>& G,
+    T (&L)[NINB][Shape<T, HV, SPMV, NR>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
+    const bool pf_next, const int64_t next_row0) {
   typedef Shape<T, HV, SPMV, NR> S;
   constexpr bool HEAVY = S::HEAVY;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
@@ -170,9 +208,20 @@ __device__ __forceinline__ void vm_step(
     if (g_ == 0) gset<T, GS>(R0[a], (e) % GS, x); else if (g_ == 1) gset<T, GS>(R1[a], (e) % GS, x); \
     else if (g_ == 2) gset<T, GS>(R2[a], (e) % GS, x); else gset<T, GS>(R3[a], (e) % GS, x); }
 
-  // ---- loads: every load of the step in flight before the first wait --------
-  if (mode != MODE_SLOW) {
-    T L[NINB][E];
+  // ---- loads ------------------------------------------------------------------
+  if (mode != MODE_SLOW && SPLIT) {
+    // issued by the caller (or prefetched by the previous step) into L
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      if (a >= P.n_in) break;
+#pragma unroll
+      for (int e = 0; e < E; ++e) RSET(a, e, L[a][e]);
+    }
+    if (pf_next) vm_load<T, V, U, E, NINB>(P, L, next_row0, c0, (1u << E) - 1, MODE_FAST);
+  } else if (mode != MODE_SLOW) {
+    // every stream of the bucket, padding slots from a zero page, in flight
+    // before the first wait
+    T Ls[NINB][E];
     bool okv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
@@ -187,19 +236,19 @@ __device__ __forceinline__ void vm_step(
         if (mode == MODE_CLAMP) p = okv[u] ? p : b;
         const vecA w = *(const vecA*)p;
 #pragma unroll
-        for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
+        for (int v = 0; v < V; ++v) Ls[a][u * V + v] = w[v];
       }
     }
     if (mode == MODE_CLAMP) {
 #pragma unroll
       for (int a = 0; a < NINB; ++a)
 #pragma unroll
-        for (int e = 0; e < E; ++e) L[a][e] = ((vmask >> e) & 1) ? L[a][e] : (T)0;
+        for (int e = 0; e < E; ++e) Ls[a][e] = ((vmask >> e) & 1) ? Ls[a][e] : (T)0;
     }
 #pragma unroll
     for (int a = 0; a < NINB; ++a)
 #pragma unroll
-      for (int e = 0; e < E; ++e) RSET(a, e, L[a][e]);
+      for (int e = 0; e < E; ++e) RSET(a, e, Ls[a][e]);
   } else {
     for (int a = 0; a < P.n_in; ++a) {
       const T* b = (const T*)P.in[a].base;
@@ -404,12 +453,24 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   const int64_t t_begin = gw * P.tiles_per_wave;
   const int64_t t_end = min(t_begin + P.tiles_per_wave, P.n_tiles);
 
+  // Arithmetic passes are stream-bound: their loads are software-pipelined
+  // one step ahead inside a tile (up to four streams: the wider bucket would
+  // lose a wave of occupancy to the prefetch registers).
+#ifndef DFX_PREFETCH_MAX_STREAMS
+#define DFX_PREFETCH_MAX_STREAMS 4
+#endif
+  constexpr bool PF = !S::HEAVY && !SPMV && NINB <= DFX_PREFETCH_MAX_STREAMS;
+  // Transcendental kernels also load through vm_load (padding slots skipped),
+  // without prefetching: their time goes to arithmetic.
+  constexpr bool SPLIT = PF || (S::HEAVY && !SPMV);
+  T L[NINB][E];
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int64_t tr = t / P.strips;
     const int64_t ts = t - tr * P.strips;
     const int64_t cbase = ts * TW;
     const int64_t c0 = cbase + (int64_t)lane * V;
     G.acc0 = G.acc1 = G.acc2 = G.acc3 = (T)0;
+    bool have = false;  // L already holds this step's values (prefetched)
     for (int r = 0; r < RED_TH; r += U) {
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= P.rows) break;
@@ -427,7 +488,16 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
           vmask |= (ok ? 1u : 0u) << e;
         }
       }
-      vm_step<T, HV, SPMV, NR, NINB>(P, R0, R1, R2, R3, G, row0, c0, vmask, mode);
+      bool next_fast = false;
+      if constexpr (SPLIT)
+        if (mode != MODE_SLOW && !(have && mode == MODE_FAST)) vm_load<T, V, U, E, NINB>(P, L, row0, c0, vmask, mode);
+      if constexpr (PF) {
+        const int64_t nr = row0 + U;
+        next_fast = r + U < RED_TH && P.unit_cols &&
+                    (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
+      }
+      vm_step<T, HV, SPMV, NR, NINB, SPLIT>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U);
+      have = next_fast;
     }
     // ---- tile sums into the block's LDS row ---------------------------------------
     if (P.n_red > 0) {
