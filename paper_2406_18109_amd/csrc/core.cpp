@@ -887,16 +887,22 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   // emit kernel instructions with operand forwarding
   out.code.clear();
   for (size_t i = 0; i < code.size(); ++i) {
-    const SInstr& I = code[i];
+    SInstr I = code[i];
     unsigned flags = 0, ra = 0, rb = 0, rd = 0;
     const int prev = i > 0 ? code[i - 1].dst : -1;
+    const bool binary = I.op == VO_ADD || I.op == VO_SUB || I.op == VO_MUL || I.op == VO_DIV ||
+                        I.op == VO_MAX || I.op == VO_MIN || I.op == VO_REDPROD || I.op == VO_POW;
+    // IEEE addition and multiplication are commutative bit for bit: put the
+    // forwarded operand first so it stays in the accumulator
+    if (binary && (I.op == VO_ADD || I.op == VO_MUL || I.op == VO_REDPROD) && I.b == prev && I.a != prev)
+      std::swap(I.a, I.b);
     if (I.a >= 0) {
       if (I.a == prev) flags |= VF_A_ACC;
-      else ra = (unsigned)vals[I.a].reg;
+      else { ra = (unsigned)vals[I.a].reg; flags |= VF_A_REG; }
     }
-    if (I.b >= 0) {
+    if (binary && I.b >= 0) {
       if (I.b == prev) flags |= VF_B_ACC;
-      else rb = (unsigned)vals[I.b].reg;
+      else { rb = (unsigned)vals[I.b].reg; flags |= VF_B_REG; }
     }
     if (I.dst >= 0 && vals[I.dst].wb) {
       flags |= VF_WB;

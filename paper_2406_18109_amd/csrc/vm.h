@@ -51,10 +51,14 @@ enum VmOp : uint8_t {
 };
 constexpr int VO_FIRST_HEAVY = VO_SQRT;
 
+// The interpreter is an accumulator machine: the previous instruction's
+// result stays in the accumulator, which each instruction updates in place.
 enum VmFlag : uint8_t {
-  VF_A_ACC = 1,   // operand a is the previous instruction's result
+  VF_A_ACC = 1,   // operand a is the previous instruction's result (the accumulator)
   VF_B_ACC = 2,   // operand b is the previous instruction's result
-  VF_WB = 4       // write the result to register dst
+  VF_WB = 4,      // write the result to register dst
+  VF_B_REG = 8,   // operand b is register b (binary ops)
+  VF_A_REG = 16   // operand a is register a: loaded into the accumulator first
 };
 
 // One instruction, four 32-bit words fetched with one scalar load:

@@ -283,62 +283,63 @@ __device__ __forceinline__ void vm_step(
     T k;
     if constexpr (sizeof(T) == 8) k = __builtin_bit_cast(double, ((uint64_t)w3 << 32) | w2);
     else k = __builtin_bit_cast(float, w2);
-    gvec x[NG], y[NG], z[NG];
-    if (flags & VF_A_ACC) {
-#pragma unroll
-      for (int g = 0; g < NG; ++g) x[g] = G.z[g];
-    } else {
-      FOR_G(x[g] = Rg[ia];)
-    }
+    // Accumulator machine: G.z holds the previous result and becomes this
+    // instruction's result in place.  Operand a is the accumulator unless it
+    // comes from a register (indexed read straight into G.z); operand b is
+    // fetched only by binary ops, and is the previous result only when the
+    // planner could not make it operand a.
+    gvec y[NG];
     if (flags & VF_B_ACC) {
 #pragma unroll
       for (int g = 0; g < NG; ++g) y[g] = G.z[g];
-    } else {
+    } else if (flags & VF_B_REG) {
       FOR_G(y[g] = Rg[ib];)
     }
-#define VEC(EXPR) { _Pragma("unroll") for (int g = 0; g < NG; ++g) z[g] = EXPR; } break;
-#define UN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(z[e / GS], e % GS, F(gget<T, GS>(x[e / GS], e % GS))); } break;
-#define BIN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(z[e / GS], e % GS, F(gget<T, GS>(x[e / GS], e % GS), gget<T, GS>(y[e / GS], e % GS))); } break;
+    if (flags & VF_A_REG) FOR_G(G.z[g] = Rg[ia];)
+#define X(g) G.z[g]
+#define VEC(EXPR) { _Pragma("unroll") for (int g = 0; g < NG; ++g) G.z[g] = EXPR; } break;
+#define UN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS))); } break;
+#define BIN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS), gget<T, GS>(y[e / GS], e % GS))); } break;
     switch (op) {
-      case VO_MOV: VEC(x[g])
-      case VO_NEG: VEC(-x[g])
+      case VO_MOV: break;
+      case VO_NEG: VEC(-X(g))
       case VO_ABS: UN(d_abs<T>)
-      case VO_SQUARE: VEC(x[g] * x[g])
-      case VO_ADD: VEC(x[g] + y[g])
-      case VO_SUB: VEC(x[g] - y[g])
-      case VO_MUL: VEC(x[g] * y[g])
-      case VO_DIV: VEC(x[g] / y[g])
+      case VO_SQUARE: VEC(X(g) * X(g))
+      case VO_ADD: VEC(X(g) + y[g])
+      case VO_SUB: VEC(X(g) - y[g])
+      case VO_MUL: VEC(X(g) * y[g])
+      case VO_DIV: VEC(X(g) / y[g])
       case VO_MAX: BIN(d_max<T>)
       case VO_MIN: BIN(d_min<T>)
-      case VO_ADDI: VEC(x[g] + k)
-      case VO_SUBI: VEC(x[g] - k)
-      case VO_RSUBI: VEC(k - x[g])
-      case VO_MULI: VEC(x[g] * k)
-      case VO_DIVI: VEC(x[g] / k)
-      case VO_RDIVI: VEC(k / x[g])
+      case VO_ADDI: VEC(X(g) + k)
+      case VO_SUBI: VEC(X(g) - k)
+      case VO_RSUBI: VEC(k - X(g))
+      case VO_MULI: VEC(X(g) * k)
+      case VO_DIVI: VEC(X(g) / k)
+      case VO_RDIVI: VEC(k / X(g))
       case VO_FILL: VEC((gvec)k)
       case VO_RED:
       case VO_REDPROD: {
-        // sequential over the slots in canonical order, valid slots only
+        // sequential over the slots in canonical order, valid slots only; the
+        // accumulator keeps operand a
         T s = slot == 0 ? G.acc0 : slot == 1 ? G.acc1 : slot == 2 ? G.acc2 : G.acc3;
-        gvec pr[NG];
+        if (op == VO_REDPROD) {
 #pragma unroll
-        for (int g = 0; g < NG; ++g) pr[g] = op == VO_REDPROD ? x[g] * y[g] : x[g];
+          for (int e = 0; e < E; ++e)
+            if ((vmask >> e) & 1) s = s + gget<T, GS>(X(e / GS), e % GS) * gget<T, GS>(y[e / GS], e % GS);
+        } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          if ((vmask >> e) & 1) s = s + gget<T, GS>(pr[e / GS], e % GS);
+          for (int e = 0; e < E; ++e)
+            if ((vmask >> e) & 1) s = s + gget<T, GS>(X(e / GS), e % GS);
+        }
         switch (slot) {
           case 0: G.acc0 = s; break;
           case 1: G.acc1 = s; break;
           case 2: G.acc2 = s; break;
           default: G.acc3 = s; break;
         }
-#pragma unroll
-        for (int g = 0; g < NG; ++g) z[g] = x[g];
       } break;
       default:
-#pragma unroll
-        for (int g = 0; g < NG; ++g) z[g] = x[g];
         if constexpr (HEAVY) {
           switch (op) {
             case VO_SQRT: UN(d_sqrt<T>)
@@ -355,12 +356,11 @@ __device__ __forceinline__ void vm_step(
         }
         break;
     }
+#undef X
 #undef VEC
 #undef BIN
 #undef UN
-#pragma unroll
-    for (int g = 0; g < NG; ++g) G.z[g] = z[g];
-    if (flags & VF_WB) FOR_G(Rg[d] = z[g];)
+    if (flags & VF_WB) FOR_G(Rg[d] = G.z[g];)
   }
 
   // ---- stores -----------------------------------------------------------------
