@@ -270,7 +270,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="all", help="all | headline | serve | copy")
+    ap.add_argument("--legs", default="all",
+                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-rate", type=float, default=120.0)
     ap.add_argument("--log2n", type=int, default=26)
@@ -296,31 +297,46 @@ def main():
         out = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
         print(json.dumps(out))
         return
+    # legs: "all" (the default line), "headline", or a comma-separated list of
+    # bs_f64, bs_f32, jacobi, cg64, cg256, serve
+    if args.legs == "all":
+        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "serve"}
+    elif args.legs == "headline":
+        sel = set()
+    else:
+        sel = set(args.legs.split(","))
     log("black-scholes f64 fused n=2^%d" % args.log2n)
     fused = bs_leg(torch, dfx, synth, wl, np, n, "f64", True, K, W)
     log("fused", fused)
     legs = {"bs_f64_fused": fused}
-    if args.legs == "all":
+    if "bs_f64" in sel:
         log("black-scholes f64 unfused")
         legs["bs_f64_unfused"] = bs_leg(torch, dfx, synth, wl, np, n, "f64", False, max(2, K // 5), 1)
+        legs["bs_f64_fused"]["speedup_vs_unfused"] = legs["bs_f64_unfused"]["ms_per_step"] / fused["ms_per_step"]
+    if "bs_f32" in sel:
         log("black-scholes f32 fused / unfused")
         legs["bs_f32_fused"] = bs_leg(torch, dfx, synth, wl, np, n, "f32", True, K, W)
         legs["bs_f32_unfused"] = bs_leg(torch, dfx, synth, wl, np, n, "f32", False, max(2, K // 5), 1)
+        legs["bs_f32_fused"]["speedup_vs_unfused"] = (legs["bs_f32_unfused"]["ms_per_step"] /
+                                                     legs["bs_f32_fused"]["ms_per_step"])
+    if "jacobi" in sel:
         log("jacobi 8192^2 fused / unfused")
         legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, 20, True)
         legs["jacobi_unfused"] = jacobi_leg(torch, dfx, synth, np, 8192, 5, False)
+        legs["jacobi_fused"]["speedup_vs_unfused"] = (legs["jacobi_unfused"]["ms_per_sweep"] /
+                                                     legs["jacobi_fused"]["ms_per_sweep"])
+    if "cg64" in sel:
         log("cg 64^2")
         legs["cg64_unfused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, False, False)
         legs["cg64_fused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, False)
         legs["cg64_fused_graph"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, True)
+    if "cg256" in sel:
         log("cg 256^3")
         legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
+    if "serve" in sel:
         log("serving: %d CG solves, Poisson arrivals at %.0f/s" % (args.serve_requests, args.serve_rate))
         legs["serve"] = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
-        for a, b in (("bs_f64_fused", "bs_f64_unfused"), ("bs_f32_fused", "bs_f32_unfused")):
-            legs[a]["speedup_vs_unfused"] = legs[b]["ms_per_step"] / legs[a]["ms_per_step"]
-        legs["jacobi_fused"]["speedup_vs_unfused"] = legs["jacobi_unfused"]["ms_per_sweep"] / legs["jacobi_fused"]["ms_per_sweep"]
 
     log("cpu oracle sample")
     sample = 1 << 21

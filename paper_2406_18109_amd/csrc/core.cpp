@@ -1111,6 +1111,11 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.x = S(p.spmv_x).ptr;
     P.nnz = (int32_t)std::min<int64_t>(S(p.spmv_col).elems, S(p.spmv_val).elems);
     P.nx = S(p.spmv_x).elems;
+    // staging pays where many waves run at once (L2 holds x for its
+    // neighbours); a small system is latency-bound and walks CSR directly
+    // (DFX_SPMV_STAGE=0 or 1 overrides the choice)
+    const char* st = std::getenv("DFX_SPMV_STAGE");
+    P.sp_stage = st && (st[0] == '0' || st[0] == '1') ? st[0] == '1' : p.n_tiles >= 256;
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);

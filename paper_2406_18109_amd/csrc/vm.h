@@ -120,6 +120,7 @@ struct VmParams {
   const void* x;
   int32_t nnz;                     // length of colidx and val
   int64_t nx;                      // length of x
+  int32_t sp_stage;                // stage each 64-row group's CSR range in LDS
   VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
 

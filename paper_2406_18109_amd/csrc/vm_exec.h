@@ -44,6 +44,9 @@ template <typename T> __device__ __forceinline__ T d_abs(T x) { return x < (T)0 
 #ifndef DFX_TRANS8_F64_ROWS
 #define DFX_TRANS8_F64_ROWS 2
 #endif
+#ifndef DFX_TRANS8_F32_ROWS
+#define DFX_TRANS8_F32_ROWS 2
+#endif
 #ifndef DFX_ARITH_F64_GS
 #define DFX_ARITH_F64_GS 1
 #endif
@@ -60,6 +63,7 @@ template <typename T, int HV, bool SPMV, int NR_> struct Shape {
   static constexpr int FIT = 256 / (NR * V * (int)sizeof(T));
   static constexpr int U = SPMV ? 1
                          : (HEAVY && NR == VM_NREG_LIGHT && sizeof(T) == 8) ? DFX_TRANS8_F64_ROWS
+                         : (HEAVY && NR == VM_NREG_LIGHT) ? DFX_TRANS8_F32_ROWS
                          : (FIT >= 2 ? 2 : 1);
   static constexpr int E = U * V;
   // The register file is split into NG arrays of NR vectors of GS elements.
@@ -127,17 +131,100 @@ enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
 
 // y = A x for the V*64 elements of a step starting at element `base`.  The
 // row of element base + 64m + l is computed by lane l (consecutive rows on
-// consecutive lanes, so each load instruction touches few cache lines), then
-// handed to its owner in the canonical layout by shuffles.
+// consecutive lanes), then handed to its owner in the canonical layout by
+// shuffles.  Each group of 64 rows reads a contiguous CSR range; when it fits
+// SP_CAP entries the wave stages that range in LDS with coalesced 16-byte
+// nontemporal loads (every line of col and val is fetched once and does not
+// displace x in L2), and each lane walks its row from LDS.  Longer ranges read
+// CSR directly (csr_row).  Either way a row is summed sequentially in CSR
+// order, so the result does not depend on the path.
+constexpr int SP_CAP = 512;
+
 template <typename T, int V>
-__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&out)[4]) {
+__device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&out)[4], int32_t* __restrict__ scol,
+                                          T* __restrict__ sval) {
   const int lane = threadIdx.x & (WAVE - 1);
+  const int32_t* __restrict__ rowptr = P.rowptr;
+  const int32_t* __restrict__ colidx = P.colidx;
+  const T* __restrict__ val = (const T*)P.val;
+  const T* __restrict__ x = (const T*)P.x;
+  const int32_t nnz = P.nnz;
+  const uint32_t nx = (uint32_t)P.nx;
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  typedef T vv __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int VE = 16 / sizeof(T);   // values per 16-byte load
   T y[V];
 #pragma unroll
   for (int m = 0; m < V; ++m) {
-    const int64_t i = base + m * WAVE + lane;
-    y[m] = i < P.n1d ? csr_row<T>(P.rowptr, P.colidx, (const T*)P.val, (const T*)P.x, i, P.nnz, (uint32_t)P.nx)
-                     : (T)0;
+    const int64_t g0 = base + m * WAVE;   // first row of the group
+    const int64_t i = g0 + lane;
+    if (g0 >= P.n1d) { y[m] = (T)0; continue; }
+    if (!P.sp_stage) {
+      y[m] = i < P.n1d ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
+      continue;
+    }
+    // the group's range from the lanes' own row pointers (first row, last valid row)
+    const int last = (int)(min(g0 + WAVE, P.n1d) - g0) - 1;
+    const int32_t rb_raw = i < P.n1d ? rowptr[i] : 0;
+    const int32_t re_raw = i < P.n1d ? rowptr[i + 1] : 0;
+    const int32_t nb = min(max(__builtin_amdgcn_readfirstlane(rb_raw), 0), nnz);
+    const int32_t ne = min(max(__builtin_amdgcn_readlane(re_raw, last), nb), nnz);
+    const int32_t a0 = nb & ~3;
+    const int32_t cnt = ne - a0;
+    if (cnt > SP_CAP) {
+      y[m] = i < P.n1d ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
+      continue;
+    }
+    // stage [a0, ne) of col and val
+    for (int j0 = 0; j0 < cnt; j0 += 4 * WAVE) {
+      const int j = j0 + 4 * lane;
+      if (j < cnt) {
+        i4 c;
+        if (a0 + j + 3 < nnz) c = __builtin_nontemporal_load((const i4*)(colidx + a0 + j));
+        else
+          for (int t = 0; t < 4; ++t) c[t] = a0 + j + t < nnz ? colidx[a0 + j + t] : 0;
+        *(i4*)(scol + j) = c;
+      }
+    }
+    for (int j0 = 0; j0 < cnt; j0 += VE * WAVE) {
+      const int j = j0 + VE * lane;
+      if (j < cnt) {
+        vv w;
+        if (a0 + j + VE - 1 < nnz) w = __builtin_nontemporal_load((const vv*)(val + a0 + j));
+        else
+          for (int t = 0; t < VE; ++t) w[t] = a0 + j + t < nnz ? val[a0 + j + t] : (T)0;
+        *(vv*)(sval + j) = w;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    T sm = (T)0;
+    if (i < P.n1d) {
+      // clamped into the staged window: a malformed rowptr reads wrong values, never outside it
+      const int32_t rb = min(max(rb_raw, nb), ne);
+      const int32_t re = min(max(re_raw, rb), ne);
+      const int32_t b = rb - a0, e = re - a0;
+      for (int32_t k = b; k < e; k += 8) {
+        int32_t c[8];
+        T av[8], xv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int32_t kk = k + t < e ? k + t : b;
+          c[t] = scol[kk];
+          av[t] = sval[kk];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xv[t] = x[(uint32_t)c[t] < nx ? c[t] : 0];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (k + t < e) {
+            const T tv = av[t] * xv[t];
+            sm = (k + t == b) ? tv : sm + tv;
+          }
+      }
+    }
+    // every lane's reads of this group are done before the next group is staged
+    __builtin_amdgcn_wave_barrier();
+    y[m] = sm;
   }
   rows_to_owners<T, V>(y, out);
 }
@@ -196,7 +283,7 @@ __device__ __forceinline__ void vm_step(
     typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R3)[NR],
     VmState<T, Shape<T, HV, SPMV, NR>::NG, Shape<T, HV, SPMV, NR>::GS>& G,
     T (&L)[NINB][Shape<T, HV, SPMV, NR>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
-    const bool pf_next, const int64_t next_row0) {
+    const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval) {
   typedef Shape<T, HV, SPMV, NR> S;
   constexpr bool HEAVY = S::HEAVY;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
@@ -267,7 +354,7 @@ __device__ __forceinline__ void vm_step(
   if constexpr (SPMV) {
     static_assert(U == 1, "SpMV steps take one row of the tiling");
     T y[4];
-    spmv_rows<T, V>(P, row0 * TW, y);
+    spmv_rows<T, V>(P, row0 * TW, y, scol, sval);
 #pragma unroll
     for (int e = 0; e < E; ++e) RSET(NR - 1, e, y[e]);
   }
@@ -427,6 +514,9 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
   typedef typename GVec<T, GS>::type gvec;
   __shared__ T tsum[VM_MAXRED][4 * VM_MAXTPW];  // this block's tile sums
+  // SpMV kernels: per wave, the staged CSR range of one 64-row group
+  __shared__ int32_t sp_col[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
+  __shared__ T sp_val[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
 
   gvec R0[NR], R1[NR], R2[NR], R3[NR];  // groups beyond NG are unused (and dropped)
   VmState<T, NG, GS> G;
@@ -448,7 +538,13 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
   // XCD-aware numbering: consecutive blocks land on different XCDs, so give
   // each XCD a contiguous range of logical blocks (and therefore of tiles).
   int lb = blockIdx.x;
-  if ((P.grid & 7) == 0) lb = (blockIdx.x & 7) * (P.grid >> 3) + (blockIdx.x >> 3);
+  // (SpMV passes keep hardware order: the gathered vector is shared by
+  // neighbouring row blocks on every XCD through the MALL, which measured
+  // slightly faster than XCD-contiguous ranges)
+#ifndef DFX_SPMV_XCD_REMAP
+#define DFX_SPMV_XCD_REMAP 0
+#endif
+  if ((P.grid & 7) == 0 && (!SPMV || DFX_SPMV_XCD_REMAP)) lb = (blockIdx.x & 7) * (P.grid >> 3) + (blockIdx.x >> 3);
   const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + wib;
   const int64_t t_begin = gw * P.tiles_per_wave;
   const int64_t t_end = min(t_begin + P.tiles_per_wave, P.n_tiles);
@@ -496,7 +592,8 @@ __global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
         next_fast = r + U < RED_TH && P.unit_cols &&
                     (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
       }
-      vm_step<T, HV, SPMV, NR, NINB, SPLIT>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U);
+      vm_step<T, HV, SPMV, NR, NINB, SPLIT>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U,
+                                            sp_col[SPMV ? wib : 0], sp_val[SPMV ? wib : 0]);
       have = next_fast;
     }
     // ---- tile sums into the block's LDS row ---------------------------------------

@@ -273,3 +273,72 @@ def test_random_windows_against_oracle(seed, shape):
         assert rel_err_floor(results[0][k], ost[k]) <= TOL_ELEM_F64, k
     for k in ("s0", "s1"):
         assert rel_err(results[0][k], ost[k]) <= TOL_RED, k
+
+
+# ---- SpMV on irregular matrices -----------------------------------------------
+
+def _irregular_csr(n, seed):
+    """Row lengths 0..12 (every 97th row empty, rows 64..191 of length 40 so some
+    64-row groups exceed the kernel's staged range), sorted distinct columns."""
+    u = synth.uniform(seed, 0, n, 0.0, 1.0)
+    lengths = np.floor(u * 13).astype(np.int64)
+    lengths[::97] = 0
+    lengths[64:192] = 40
+    lengths = np.minimum(lengths, n)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(lengths)
+    nnz = int(rowptr[-1])
+    cu = synth.uniform(seed, 1, nnz, 0.0, 1.0)
+    col = np.empty(nnz, dtype=np.int32)
+    for i in range(n):
+        b, e = rowptr[i], rowptr[i + 1]
+        if e > b:
+            # distinct sorted columns: a stride walk from a random start
+            start = int(cu[b] * n)
+            step = max(1, n // max(1, e - b))
+            col[b:e] = np.sort((start + step * np.arange(e - b)) % n)
+    val = synth.uniform(seed, 2, nnz, -1.0, 1.0)
+    return rowptr.astype(np.int32), col, val
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1000, 4095, 20000])
+def test_spmv_dot_irregular_rows(dtype, n, monkeypatch):
+    """Fused and unfused, with the CSR range of each 64-row group staged in LDS
+    and read directly: identical bits, and the oracle's sequential CSR sum."""
+    note("spmv irregular n=%d %s" % (n, dtype))
+    from oracle import cnum
+    npdt = np.float64 if dtype == "f64" else np.float32
+    rowptr, col, val = _irregular_csr(n, 40 + n)
+    x = synth.uniform(41 + n, 0, n, -1.0, 1.0)
+    outs = []
+    for fuse, stage in ((True, "1"), (False, "1"), (True, "0")):
+        monkeypatch.setenv("DFX_SPMV_STAGE", stage)
+        c = ctx(fuse=fuse, window=8)
+        hr, hc = upload(c, rowptr), upload(c, col)
+        hv, hx = upload(c, val.astype(npdt)), upload(c, x.astype(npdt))
+        hy = c.store_create([n], dtype)
+        hs = c.store_create([], dtype)
+        N = c.part_none()
+        T = c.part_tiling([n])
+        img = c.part_image(hc, N)
+        c.submit("spmv_csr", [1], [(hr, N, "R"), (hc, N, "R"), (hv, N, "R"), (hx, img, "R"), (hy, T, "W")])
+        c.submit("dot", [1], [(hx, T, "R"), (hy, T, "R"), (hs, N, "Rd")], (1,))
+        c.flush()
+        outs.append((c.store_read(hy, [n], dtype), c.store_read(hs, [], dtype)))
+        c.close()
+    for k in (1, 2):
+        assert np.array_equal(outs[0][0], outs[k][0])
+        assert np.array_equal(outs[0][1], outs[k][1])
+    yo = cnum.spmv(rowptr, col, val.astype(npdt).astype(np.float64), x.astype(npdt).astype(np.float64))
+    so = cnum.fsum_prod(x.astype(npdt).astype(np.float64), yo)
+    # the dot of random-sign vectors may cancel: its error is measured against
+    # the sum of the magnitudes of its terms
+    scale = cnum.fsum(np.abs(x.astype(npdt).astype(np.float64) * yo))
+    if dtype == "f64":
+        # the same sequential CSR sum in the same precision: identical bits
+        assert np.array_equal(outs[0][0], yo)
+        assert abs(float(outs[0][1]) - so) <= TOL_RED * scale
+    else:
+        assert rel_err_floor(outs[0][0], yo) <= TOL_ELEM_F32
+        assert abs(float(outs[0][1]) - so) <= 1e-4 * scale
