@@ -885,7 +885,13 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   out.nreg = 0;
   for (auto& v : vals) out.nreg = std::max(out.nreg, v.reg + 1);
   // emit kernel instructions with operand forwarding
-  out.code.clear();
+  struct EI {
+    unsigned op, flags, d, a, b, slot;
+    double imm;
+    bool uses_imm;
+    unsigned post = 0, c = 0;
+  };
+  std::vector<EI> em;
   for (size_t i = 0; i < code.size(); ++i) {
     SInstr I = code[i];
     unsigned flags = 0, ra = 0, rb = 0, rd = 0;
@@ -908,10 +914,42 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
       flags |= VF_WB;
       rd = (unsigned)vals[I.dst].reg;
     }
+    const bool uses_imm = I.op == VO_ADDI || I.op == VO_SUBI || I.op == VO_RSUBI || I.op == VO_MULI ||
+                          I.op == VO_DIVI || I.op == VO_RDIVI || I.op == VO_FILL;
     const double immv = I.imm >= 0 && I.imm < (int)out.imm.size() ? out.imm[I.imm] : 0.0;
-    VmInstr K = vm_instr(I.op, rd, ra, rb, flags, (unsigned)I.slot, immv, dtype == DFX_F64);
-    out.code.push_back(K);
+    em.push_back(EI{I.op, flags, rd, ra, rb, (unsigned)I.slot, immv, uses_imm});
   }
+  // two-op superinstructions: an op whose result only feeds the next op as
+  // its operand a carries that op as its post op (operand b of a binary post
+  // op from register c), when at most one of the two uses the immediate
+  auto post_ok = [](unsigned op) {
+    return op == VO_NEG || op == VO_SQUARE || op == VO_ADDI || op == VO_SUBI || op == VO_RSUBI ||
+           op == VO_MULI || op == VO_ADD || op == VO_SUB || op == VO_MUL;
+  };
+  std::vector<EI> merged;
+  for (size_t i = 0; i < em.size(); ++i) {
+    if (i + 1 < em.size()) {
+      const EI& f = em[i];
+      const EI& s2 = em[i + 1];
+      const bool first_ok = f.op != VO_RED && f.op != VO_REDPROD && !(f.flags & VF_WB);
+      const bool second_ok = post_ok(s2.op) && (s2.flags & VF_A_ACC) && !(s2.flags & (VF_A_REG | VF_B_ACC));
+      if (first_ok && second_ok && !(f.uses_imm && s2.uses_imm)) {
+        EI m = f;
+        m.post = s2.op + 1;
+        m.flags = (f.flags & (VF_A_ACC | VF_A_REG | VF_B_ACC | VF_B_REG)) | (s2.flags & VF_WB) |
+                  ((s2.flags & VF_B_REG) ? VF_C_REG : 0);
+        m.d = s2.d;
+        m.c = s2.b;
+        if (s2.uses_imm) { m.imm = s2.imm; m.uses_imm = true; }
+        merged.push_back(m);
+        ++i;
+        continue;
+      }
+    }
+    merged.push_back(em[i]);
+  }
+  for (const EI& e : merged)
+    out.code.push_back(vm_instr(e.op, e.d, e.a, e.b, e.flags, e.slot, e.imm, dtype == DFX_F64, e.post, e.c));
   for (auto& o : outs) {
     const auto key = written[o.second];
     const StoreRec& s = c.stores.at(L.order[key.first]);
@@ -968,9 +1006,9 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
                  (long long)out.tiles_per_wave, out.grid, (long long)out.alg_bytes);
     if (trace_level() > 1)
       for (auto& K : out.code)
-        std::fprintf(stderr, "dfx:   op=%u flags=%u slot=%u dst=%u a=%u b=%u imm=%08x%08x\n", K.w0 & 0xff,
-                     (K.w0 >> 8) & 0xff, (K.w0 >> 16) & 0xff, K.w1 & 0xff, (K.w1 >> 8) & 0xff,
-                     (K.w1 >> 16) & 0xff, K.w3, K.w2);
+        std::fprintf(stderr, "dfx:   op=%u flags=%u slot=%u post=%u dst=%u a=%u b=%u c=%u imm=%08x%08x\n",
+                     K.w0 & 0xff, (K.w0 >> 8) & 0xff, (K.w0 >> 16) & 0xff, K.w0 >> 24, K.w1 & 0xff,
+                     (K.w1 >> 8) & 0xff, (K.w1 >> 16) & 0xff, K.w1 >> 24, K.w3, K.w2);
   }
   return DFX_OK;
 }

@@ -58,19 +58,23 @@ enum VmFlag : uint8_t {
   VF_B_ACC = 2,   // operand b is the previous instruction's result
   VF_WB = 4,      // write the result to register dst
   VF_B_REG = 8,   // operand b is register b (binary ops)
-  VF_A_REG = 16   // operand a is register a: loaded into the accumulator first
+  VF_A_REG = 16,  // operand a is register a: loaded into the accumulator first
+  VF_C_REG = 32   // the post op's operand b is register c
 };
 
 // One instruction, four 32-bit words fetched with one scalar load:
-//   w0 = op | flags << 8 | slot << 16     (slot: reduction slot of RED/REDPROD)
-//   w1 = dst | a << 8 | b << 16           (register indices, extracted by bit-field)
+//   w0 = op | flags << 8 | slot << 16 | post << 24
+//   w1 = dst | a << 8 | b << 16 | c << 24  (register indices, extracted by bit-field)
 //   w2, w3 = the immediate in the pass's element type (FP32: w2 only)
+// slot is the reduction slot of RED/REDPROD.  post (0 = none, else a VmOp + 1)
+// is a second op applied to the accumulator after the first, with operand b
+// from register c when it is binary (a two-op superinstruction).
 struct VmInstr {
   uint32_t w0, w1, w2, w3;
 };
 inline VmInstr vm_instr(unsigned op, unsigned dst, unsigned a, unsigned b, unsigned flags, unsigned slot,
-                        double imm, bool f64) {
-  VmInstr I{op | flags << 8 | slot << 16, dst | a << 8 | b << 16, 0, 0};
+                        double imm, bool f64, unsigned post = 0, unsigned c = 0) {
+  VmInstr I{op | flags << 8 | slot << 16 | post << 24, dst | a << 8 | b << 16 | c << 24, 0, 0};
   if (f64) {
     uint64_t u;
     __builtin_memcpy(&u, &imm, 8);

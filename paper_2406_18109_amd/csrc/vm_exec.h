@@ -365,8 +365,9 @@ __device__ __forceinline__ void vm_step(
     const unsigned w0 = __builtin_amdgcn_readfirstlane(nx.w0), w1 = __builtin_amdgcn_readfirstlane(nx.w1);
     const unsigned w2 = __builtin_amdgcn_readfirstlane(nx.w2), w3 = __builtin_amdgcn_readfirstlane(nx.w3);
     nx = P.code[pc + 1];
-    const unsigned op = w0 & 0xff, flags = (w0 >> 8) & 0xff, slot = (w0 >> 16) & 0xff;
-    const unsigned d = w1 & 0xff, ia = (w1 >> 8) & 0xff, ib = (w1 >> 16) & 0xff;
+    const unsigned flags = (w0 >> 8) & 0xff, slot = (w0 >> 16) & 0xff, post = w0 >> 24;
+    const unsigned d = w1 & 0xff, ia = (w1 >> 8) & 0xff, ib = (w1 >> 16) & 0xff, ic = w1 >> 24;
+    const unsigned op = w0 & 0xff;
     T k;
     if constexpr (sizeof(T) == 8) k = __builtin_bit_cast(double, ((uint64_t)w3 << 32) | w2);
     else k = __builtin_bit_cast(float, w2);
@@ -442,6 +443,22 @@ __device__ __forceinline__ void vm_step(
           }
         }
         break;
+    }
+    // superinstruction: a cheap follow-up op on the accumulator
+    if (post != 0) {
+      if (flags & VF_C_REG) FOR_G(y[g] = Rg[ic];)
+      switch (post - 1) {
+        case VO_NEG: VEC(-X(g))
+        case VO_SQUARE: VEC(X(g) * X(g))
+        case VO_ADD: VEC(X(g) + y[g])
+        case VO_SUB: VEC(X(g) - y[g])
+        case VO_MUL: VEC(X(g) * y[g])
+        case VO_ADDI: VEC(X(g) + k)
+        case VO_SUBI: VEC(X(g) - k)
+        case VO_RSUBI: VEC(k - X(g))
+        case VO_MULI: VEC(X(g) * k)
+        default: break;
+      }
     }
 #undef X
 #undef VEC
