@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "dev_common.h"
+#include "dmath.h"
 #include "vm.h"
 
 namespace dfx {
@@ -28,10 +29,10 @@ template <typename T> __device__ __forceinline__ T d_exp(T x);
 template <> __device__ __forceinline__ double d_exp<double>(double x) { return exp(x); }
 template <> __device__ __forceinline__ float d_exp<float>(float x) { return expf(x); }
 template <typename T> __device__ __forceinline__ T d_log(T x);
-template <> __device__ __forceinline__ double d_log<double>(double x) { return log(x); }
+template <> __device__ __forceinline__ double d_log<double>(double x) { return dm_log(x); }
 template <> __device__ __forceinline__ float d_log<float>(float x) { return logf(x); }
 template <typename T> __device__ __forceinline__ T d_erf(T x);
-template <> __device__ __forceinline__ double d_erf<double>(double x) { return erf(x); }
+template <> __device__ __forceinline__ double d_erf<double>(double x) { return dm_erf(x); }
 template <> __device__ __forceinline__ float d_erf<float>(float x) { return erff(x); }
 template <typename T> __device__ __forceinline__ T d_pow(T x, T y);
 template <> __device__ __forceinline__ double d_pow<double>(double x, double y) { return pow(x, y); }
