@@ -1,4 +1,4 @@
-// FP64 log and erf for the op-list kernels.
+// FP64 log, exp and erf for the op-list kernels.
 //
 // Both are branch-free (every lane of a wave runs the same instructions)
 // and keep their working precision in plain doubles; the constants come
@@ -56,13 +56,23 @@ __device__ __forceinline__ double dm_log(double x) {
   return x != x ? x : y;
 }
 
-// exp(y) for y in [-36, -0.7]: y = n ln 2 + r with |r| <= ln2 / 2, the
-// result a normal double (no overflow, underflow or special inputs)
+// exp(y) for finite y in [-746, 710]: y = n ln 2 + r with |r| <= ln2 / 2,
+// exp y = 2^n E(r), one rounding in the final scaling
 __device__ __forceinline__ double dm_exp_mid(double y) {
   const double n = __builtin_rint(y * dmc::INV_LN2);
   double r = __builtin_fma(-n, dmc::LN2_HI, y);
   r = __builtin_fma(-n, dmc::LN2_LO, r);
   return __builtin_amdgcn_ldexp(dm_poly(dmc::EXP_E, r), (int)n);
+}
+
+// Exponential over the whole double range: x is clamped to [-746, 710]
+// (beyond, the result is 0 or inf anyway), reduced to x = n ln 2 + r with
+// |r| <= ln2 / 2, and scaled by one ldexp, which also rounds results in
+// the overflow and denormal range.
+__device__ __forceinline__ double dm_exp(double x) {
+  const double xc = x < -746.0 ? -746.0 : (x > 710.0 ? 710.0 : x);
+  const double y = dm_exp_mid(xc);
+  return x != x ? x : y;
 }
 
 // Error function.  |x| < 0.84375: erf x = x P(x^2).  Above: erf |x| =

@@ -26,7 +26,7 @@ template <typename T> __device__ __forceinline__ T d_sqrt(T x);
 template <> __device__ __forceinline__ double d_sqrt<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float d_sqrt<float>(float x) { return sqrtf(x); }
 template <typename T> __device__ __forceinline__ T d_exp(T x);
-template <> __device__ __forceinline__ double d_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ double d_exp<double>(double x) { return dm_exp(x); }
 template <> __device__ __forceinline__ float d_exp<float>(float x) { return expf(x); }
 template <typename T> __device__ __forceinline__ T d_log(T x);
 template <> __device__ __forceinline__ double d_log<double>(double x) { return dm_log(x); }

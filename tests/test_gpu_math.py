@@ -99,7 +99,10 @@ def test_erf_f64():
 
 
 def test_exp_sqrt_f64():
-    x = np.concatenate([synth.uniform(31, 0, 1 << 17, -745.5, 709.9), _around(0.0, 100), np.array(SPECIALS)])
+    x = np.concatenate([synth.uniform(31, 0, 1 << 17, -745.5, 709.9), _around(0.0, 100),
+                        _around(709.782712893384, 300), _around(-708.3964185322641, 300),   # overflow, denormal
+                        _around(-745.1332191019411, 300), _around(-746.0, 50), _around(710.0, 50),
+                        np.array(SPECIALS)])
     _check("exp", x, _run("exp", x), cnum.exp(x), 2)
     y = np.concatenate([_bits(32, 1 << 17, 0, 0x7FF0000000000000), np.array(SPECIALS)])
     with np.errstate(invalid="ignore"):   # the negative specials
