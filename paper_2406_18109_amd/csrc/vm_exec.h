@@ -26,13 +26,13 @@ template <typename T> __device__ __forceinline__ T d_sqrt(T x);
 template <> __device__ __forceinline__ double d_sqrt<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float d_sqrt<float>(float x) { return sqrtf(x); }
 template <typename T> __device__ __forceinline__ T d_exp(T x);
-template <> __device__ __forceinline__ double d_exp<double>(double x) { return dm_exp(x); }
+template <> __device__ __forceinline__ double d_exp<double>(double x) { double v[1] = {x}; dm_exp(v); return v[0]; }
 template <> __device__ __forceinline__ float d_exp<float>(float x) { return expf(x); }
 template <typename T> __device__ __forceinline__ T d_log(T x);
-template <> __device__ __forceinline__ double d_log<double>(double x) { return dm_log(x); }
+template <> __device__ __forceinline__ double d_log<double>(double x) { double v[1] = {x}; dm_log(v); return v[0]; }
 template <> __device__ __forceinline__ float d_log<float>(float x) { return logf(x); }
 template <typename T> __device__ __forceinline__ T d_erf(T x);
-template <> __device__ __forceinline__ double d_erf<double>(double x) { return dm_erf(x); }
+template <> __device__ __forceinline__ double d_erf<double>(double x) { double v[1] = {x}; dm_erf(v); return v[0]; }
 template <> __device__ __forceinline__ float d_erf<float>(float x) { return erff(x); }
 template <typename T> __device__ __forceinline__ T d_pow(T x, T y);
 template <> __device__ __forceinline__ double d_pow<double>(double x, double y) { return pow(x, y); }
@@ -388,6 +388,20 @@ __device__ __forceinline__ void vm_step(
 #define X(g) G.z[g]
 #define VEC(EXPR) { _Pragma("unroll") for (int g = 0; g < NG; ++g) G.z[g] = EXPR; } break;
 #define UN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS))); } break;
+// FP64: all E elements through the lockstep form of the function at once
+#define UNW(FN, F)                                                                                 \
+  {                                                                                                \
+    if constexpr (sizeof(T) == 8) {                                                                \
+      double a_[E];                                                                                \
+      _Pragma("unroll") for (int e = 0; e < E; ++e) a_[e] = gget<T, GS>(G.z[e / GS], e % GS);     \
+      FN(a_);                                                                                      \
+      _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, (T)a_[e]);   \
+    } else {                                                                                       \
+      _Pragma("unroll") for (int e = 0; e < E; ++e)                                                \
+        gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS)));                    \
+    }                                                                                              \
+  }                                                                                                \
+  break;
 #define BIN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS), gget<T, GS>(y[e / GS], e % GS))); } break;
     switch (op) {
       case VO_MOV: break;
@@ -432,9 +446,9 @@ __device__ __forceinline__ void vm_step(
         if constexpr (HEAVY) {
           switch (op) {
             case VO_SQRT: UN(d_sqrt<T>)
-            case VO_EXP: UN(d_exp<T>)
-            case VO_LOG: UN(d_log<T>)
-            case VO_ERF: UN(d_erf<T>)
+            case VO_EXP: UNW(dm_exp, d_exp<T>)
+            case VO_LOG: UNW(dm_log, d_log<T>)
+            case VO_ERF: UNW(dm_erf, d_erf<T>)
             case VO_POW:
               if constexpr (HV >= 2) {
                 BIN(d_pow<T>)
@@ -465,6 +479,7 @@ __device__ __forceinline__ void vm_step(
 #undef VEC
 #undef BIN
 #undef UN
+#undef UNW
     if (flags & VF_WB) FOR_G(Rg[d] = G.z[g];)
   }
 
