@@ -176,26 +176,38 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
       y[m] = i < P.n1d ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
       continue;
     }
-    // stage [a0, ne) of col and val
-    for (int j0 = 0; j0 < cnt; j0 += 4 * WAVE) {
-      const int j = j0 + 4 * lane;
+    // stage [a0, ne) of col and val: every chunk's load is in flight before
+    // the first LDS store (cnt <= SP_CAP here)
+    constexpr int CC = SP_CAP / (4 * WAVE), VC = SP_CAP / (VE * WAVE);
+    i4 cb[CC];
+    vv vb[VC];
+#pragma unroll
+    for (int u = 0; u < CC; ++u) {
+      const int j = (u * WAVE + lane) * 4;
       if (j < cnt) {
-        i4 c;
-        if (a0 + j + 3 < nnz) c = __builtin_nontemporal_load((const i4*)(colidx + a0 + j));
+        if (a0 + j + 3 < nnz) cb[u] = __builtin_nontemporal_load((const i4*)(colidx + a0 + j));
         else
-          for (int t = 0; t < 4; ++t) c[t] = a0 + j + t < nnz ? colidx[a0 + j + t] : 0;
-        *(i4*)(scol + j) = c;
+          for (int t = 0; t < 4; ++t) cb[u][t] = a0 + j + t < nnz ? colidx[a0 + j + t] : 0;
       }
     }
-    for (int j0 = 0; j0 < cnt; j0 += VE * WAVE) {
-      const int j = j0 + VE * lane;
+#pragma unroll
+    for (int u = 0; u < VC; ++u) {
+      const int j = (u * WAVE + lane) * VE;
       if (j < cnt) {
-        vv w;
-        if (a0 + j + VE - 1 < nnz) w = __builtin_nontemporal_load((const vv*)(val + a0 + j));
+        if (a0 + j + VE - 1 < nnz) vb[u] = __builtin_nontemporal_load((const vv*)(val + a0 + j));
         else
-          for (int t = 0; t < VE; ++t) w[t] = a0 + j + t < nnz ? val[a0 + j + t] : (T)0;
-        *(vv*)(sval + j) = w;
+          for (int t = 0; t < VE; ++t) vb[u][t] = a0 + j + t < nnz ? val[a0 + j + t] : (T)0;
       }
+    }
+#pragma unroll
+    for (int u = 0; u < CC; ++u) {
+      const int j = (u * WAVE + lane) * 4;
+      if (j < cnt) *(i4*)(scol + j) = cb[u];
+    }
+#pragma unroll
+    for (int u = 0; u < VC; ++u) {
+      const int j = (u * WAVE + lane) * VE;
+      if (j < cnt) *(vv*)(sval + j) = vb[u];
     }
     __builtin_amdgcn_wave_barrier();
     T sm = (T)0;
@@ -541,8 +553,14 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
   return v;
 }
 
+// SpMV passes keep four waves per SIMD (one tile per wave fills the chip
+// only if all of them are resident)
+#ifndef DFX_SPMV_WAVES
+#define DFX_SPMV_WAVES 4
+#endif
 template <typename T, int HV, bool SPMV, int NR, int NINB>
-__global__ __launch_bounds__(BLOCK) void vm_kernel(const VmParams P) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SPMV && HV == 0 ? DFX_SPMV_WAVES : 1)))
+void vm_kernel(const VmParams P) {
   typedef Shape<T, HV, SPMV, NR> S;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
   typedef typename GVec<T, GS>::type gvec;
