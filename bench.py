@@ -182,7 +182,7 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
     return out
 
 
-def serve_leg(dfx, synth, np, count, rate, budget, slots):
+def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0):
     """Continuous-batching server on the first `count` requests of the serving
     stream: 2-D Poisson solves, side uniform in [32, 512], tol 1e-8, Poisson
     arrivals at `rate` per second.  Latency = completion - arrival."""
@@ -191,7 +191,7 @@ def serve_leg(dfx, synth, np, count, rate, budget, slots):
     arrivals = synth.serve_arrivals(count, rate)
     mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
     c = dfx.Context(device=0)
-    c.serve_start(hbm_budget=budget, max_slots=slots, tol=1e-8, max_iter=20000)
+    c.serve_start(hbm_budget=budget, max_slots=slots, tol=1e-8, max_iter=20000, iters_per_round=ipr)
     tickets = [None] * count
 
     def feeder():
@@ -225,6 +225,7 @@ def serve_leg(dfx, synth, np, count, rate, budget, slots):
     return {"requests": count, "converged": ok, "arrival_rate_per_s": rate, "solves_per_s": count / wall,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_iterations": float(its.mean()), "rounds": st["rounds"], "launches": st["launches"],
+            "iters_per_round": ipr,
             "peak_bytes": st["peak_bytes"], "hbm_budget": budget, "max_slots": slots, "wall_s": wall}
 
 
@@ -274,6 +275,8 @@ def main():
                     help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-rate", type=float, default=120.0)
+    ap.add_argument("--serve-iters-per-round", type=int, default=0,
+                    help="CG iterations per scheduling round (0: the library default)")
     ap.add_argument("--log2n", type=int, default=26)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -294,7 +297,7 @@ def main():
         print(json.dumps(copy_leg(dfx, np, torch, n, K)))
         return
     if args.legs == "serve":
-        out = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
+        out = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64, args.serve_iters_per_round)
         print(json.dumps(out))
         return
     # legs: "all" (the default line), "headline", or a comma-separated list of
@@ -336,7 +339,8 @@ def main():
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
     if "serve" in sel:
         log("serving: %d CG solves, Poisson arrivals at %.0f/s" % (args.serve_requests, args.serve_rate))
-        legs["serve"] = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64)
+        legs["serve"] = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64,
+                                  args.serve_iters_per_round)
 
     log("cpu oracle sample")
     sample = 1 << 21

@@ -245,7 +245,12 @@ typedef struct {
   int32_t max_slots;     /* solves resident at once */
   int32_t max_iter;      /* iteration limit per solve */
   double tol;            /* relative residual target */
-  int32_t reserved[8];
+  int32_t iters_per_round;  /* CG iterations per scheduling round, 0 for the default
+                               (8); status checks, retirement and admission happen
+                               between rounds, and a solve that converges inside a
+                               round stops iterating on the device, so results do
+                               not depend on it */
+  int32_t reserved[7];
 } dfx_serve_cfg;
 
 /* Host CSR arrays: validated and referenced (not copied) by submit; they must

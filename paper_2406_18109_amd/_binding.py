@@ -69,7 +69,7 @@ class dfx_group_info(C.Structure):
 
 class dfx_serve_cfg(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("max_iter", C.c_int32),
-                ("tol", C.c_double), ("reserved", C.c_int32 * 8)]
+                ("tol", C.c_double), ("iters_per_round", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class dfx_csr_desc(C.Structure):
@@ -351,8 +351,9 @@ class Context:
         self._chk(self.L.dfx_stats_reset(self.h))
 
     # -- serving ------------------------------------------------------------------
-    def serve_start(self, hbm_budget: int, max_slots: int = 256, tol: float = 1e-8, max_iter: int = 100000):
-        cfg = dfx_serve_cfg(hbm_budget, max_slots, max_iter, tol)
+    def serve_start(self, hbm_budget: int, max_slots: int = 256, tol: float = 1e-8, max_iter: int = 100000,
+                    iters_per_round: int = 0):
+        cfg = dfx_serve_cfg(hbm_budget, max_slots, max_iter, tol, iters_per_round)
         self._chk(self.L.dfx_serve_start(self.h, C.byref(cfg)))
         self._serve_keep = {}
 

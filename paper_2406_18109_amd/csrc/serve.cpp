@@ -275,15 +275,20 @@ static void scheduler(Server* Sp) {
               hipMemcpyAsync(S.d_fin, S.h_fin, 2 * ms * sizeof(int32_t), hipMemcpyHostToDevice, S.stream) == hipSuccess;
     int e = ok ? 0 : 1;
     if (!e) e = run_phase(S, PH_INIT, (int64_t)n_new, 0);
-    if (!e) e = run_phase(S, PH_SPMV_DOT, (int64_t)n_all, (int64_t)n_new);
-    if (!e) e = run_phase(S, PH_AXPY_DOT, (int64_t)n_all, (int64_t)n_new);
-    if (!e) e = run_phase(S, PH_UPDATE_P, (int64_t)n_all, (int64_t)n_new);
+    // several iterations per round amortise the host round trip; a solve that
+    // converges inside the round is skipped by the remaining phases
+    const int ipr = S.cfg.iters_per_round > 0 ? S.cfg.iters_per_round : 8;
+    for (int j = 0; j < ipr && !e; ++j) {
+      e = run_phase(S, PH_SPMV_DOT, (int64_t)n_all, (int64_t)n_new);
+      if (!e) e = run_phase(S, PH_AXPY_DOT, (int64_t)n_all, (int64_t)n_new);
+      if (!e) e = run_phase(S, PH_UPDATE_P, (int64_t)n_all, (int64_t)n_new);
+    }
     // one transfer of every slot's state (unused slots are ignored below)
     if (!e) e = hipMemcpyAsync(S.h_solves, S.d_solves, sizeof(SolveDev) * S.slots.size(), hipMemcpyDeviceToHost, S.stream);
     if (!e) e = hipStreamSynchronize(S.stream);
     if (e) { std::lock_guard<std::mutex> lk(S.mu); fail_locked(S, "round failed: " + std::string(hipGetErrorString((hipError_t)e))); break; }
     S.stats.rounds += 1;
-    S.stats.row_updates += n_all * (int64_t)(RED_TH * 128);
+    S.stats.row_updates += (int64_t)ipr * n_all * (int64_t)(RED_TH * 128);
     // ---- retire finished solves ---------------------------------------------------
     for (size_t i = 0; i < S.slots.size(); ++i) {
       ServeSlot& sl = S.slots[i];
@@ -327,7 +332,7 @@ int dfx_serve_start(dfx_ctx* c, const dfx_serve_cfg* cfg) {
   if (!c || !cfg) return DFX_EINVAL;
   if (c->analysis_only) { c->err = "serving needs a device"; return DFX_ESTATE; }
   if (c->server) { c->err = "server already running"; return DFX_ESTATE; }
-  if (cfg->max_slots < 1 || cfg->hbm_budget == 0 || !(cfg->tol > 0) || cfg->max_iter < 1) {
+  if (cfg->max_slots < 1 || cfg->hbm_budget == 0 || !(cfg->tol > 0) || cfg->max_iter < 1 || cfg->iters_per_round < 0) {
     c->err = "bad serving configuration";
     return DFX_EINVAL;
   }

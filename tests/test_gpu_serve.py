@@ -78,6 +78,31 @@ def test_alone_equals_mix_and_matches_oracle():
     c.close()
 
 
+def test_iterations_per_round_do_not_change_results():
+    """A solve that converges inside a multi-iteration round stops on the
+    device: x, the iteration count and the residual are those of one
+    iteration per round."""
+    sides = [40, 23, 8, 57]
+    mats = {s: synth.poisson_csr(s, 2) for s in sides}
+    out = {}
+    for ipr in (1, 7):
+        c = ctx()
+        c.serve_start(hbm_budget=1 << 30, max_slots=4, tol=TOL, max_iter=4000, iters_per_round=ipr)
+        note("serve iters_per_round=%d" % ipr)
+        tickets = [(c.serve_submit(*mats[s], synth.serve_rhs(50 + i, s * s)), s) for i, s in enumerate(sides)]
+        out[ipr] = [(c.serve_wait(t, 300), c.serve_read_x(t, s * s)) for t, s in tickets]
+        rounds = c.serve_stats()["rounds"]
+        out[ipr].append(rounds)
+        c.serve_stop()
+        c.close()
+    for (r1, x1), (r7, x7) in zip(out[1][:-1], out[7][:-1]):
+        assert r1["status"] == r7["status"] == B.SOLVE_CONVERGED
+        assert r1["iterations"] == r7["iterations"]
+        assert r1["rel_residual"] == r7["rel_residual"]
+        assert np.array_equal(x1, x7)
+    assert out[7][-1] < out[1][-1]
+
+
 def test_admission_binds_to_budget():
     c = ctx()
     s = 96
