@@ -63,6 +63,49 @@ __device__ __forceinline__ T csr_row(const int32_t* __restrict__ rowptr, const i
   return s;
 }
 
+// N rows per lane at once (row i[m] when ok[m]), each summed exactly as
+// csr_row sums it; the rows' loads are issued together, so their memory
+// latencies overlap.  Entries past a row's end read index 0, which exists
+// whenever any row of the call has an entry.
+template <typename T, int N>
+__device__ __forceinline__ void csr_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                         const T* __restrict__ val, const T* __restrict__ x, const int64_t (&i)[N],
+                                         const bool (&ok)[N], int32_t nnz, uint32_t nx, T (&y)[N]) {
+  int32_t rb[N], len[N], lmax = 0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int32_t b0 = ok[m] ? rowptr[i[m]] : 0, e0 = ok[m] ? rowptr[i[m] + 1] : 0;
+    rb[m] = min(max(b0, 0), nnz);
+    len[m] = min(max(e0, rb[m]), nnz) - rb[m];
+    lmax = max(lmax, len[m]);
+    y[m] = (T)0;
+  }
+  for (int32_t k = 0; k < lmax; k += 8) {
+    int32_t c[N][8];
+    T a[N][8], xv[N][8];
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int32_t idx = k + j < len[m] ? rb[m] + k + j : 0;
+        c[m][j] = colidx[idx];
+        a[m][j] = val[idx];
+      }
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[m][j] = x[(uint32_t)c[m][j] < nx ? c[m][j] : 0];
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k + j < len[m]) {
+          const T t = a[m][j] * xv[m][j];
+          y[m] = (k + j == 0) ? t : y[m] + t;
+        }
+  }
+}
+
 // Move per-lane row results to the canonical owners: y[m] of lane l holds the
 // element 64m + l of a run of V*64 elements; lane l receives elements V*l + v
 // (v < V) in out[v].

@@ -40,62 +40,104 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
     double* __restrict__ p = S->p;
     double* __restrict__ q = S->q;
     const double alpha = S->alpha, beta = S->beta;
+    const int64_t t0 = (int64_t)tile * S_TH * S_TW;
+    const int nrows = (int)min((int64_t)S_TH, (n - t0 + S_TW - 1) / S_TW);  // rows of the tile inside n
     double acc = 0.0;
     if (phase == PH_SPMV_DOT) {
-      // q = A p with consecutive rows on consecutive lanes, then p.q in the
-      // canonical order (lane l owns elements 2l, 2l+1 of each row)
+      // q = A p with consecutive rows on consecutive lanes (two tile rows,
+      // four 64-row groups, per call), then p.q in the canonical order (lane
+      // l owns elements 2l, 2l+1 of each row)
       const int32_t nnz = S->rowptr[n];
-      for (int rr = 0; rr < S_TH; ++rr) {
-        const int64_t sb = ((int64_t)tile * S_TH + rr) * S_TW;
-        if (sb >= n) break;
-        double y[2], qo[4];
+      for (int r0 = 0; r0 < nrows; r0 += 2) {
+        int64_t gi[4];
+        bool gok[4];
+        double y[4], pv[2][2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const int64_t i = sb + m * WAVE + lane;
-          y[m] = i < n ? csr_row<double>(S->rowptr, S->col, S->val, p, i, nnz, (uint32_t)n) : 0.0;
-          if (i < n) q[i] = y[m];
+        for (int m = 0; m < 4; ++m) {
+          gi[m] = t0 + (int64_t)(r0 + m / 2) * S_TW + (m % 2) * WAVE + lane;
+          gok[m] = r0 + m / 2 < nrows && gi[m] < n;
         }
-        rows_to_owners<double, 2>(y, qo);
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const int64_t i = sb + 2 * lane + v;
-          if (i < n) {
-            const double t = p[i] * qo[v];
-            acc = acc + t;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int64_t i = t0 + (int64_t)(r0 + h) * S_TW + 2 * lane + v;
+            pv[h][v] = r0 + h < nrows && i < n ? p[i] : 0.0;
+          }
+        csr_rows<double, 4>(S->rowptr, S->col, S->val, p, gi, gok, nnz, (uint32_t)n, y);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (gok[m]) q[gi[m]] = y[m];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (r0 + h >= nrows) break;
+          const double yy[2] = {y[2 * h], y[2 * h + 1]};
+          double qo[4];
+          rows_to_owners<double, 2>(yy, qo);
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int64_t i = t0 + (int64_t)(r0 + h) * S_TW + 2 * lane + v;
+            if (i < n) {
+              const double t = pv[h][v] * qo[v];
+              acc = acc + t;
+            }
           }
         }
       }
-    }
-    for (int rr = 0; rr < S_TH && phase != PH_SPMV_DOT; ++rr) {
-      const int64_t base = ((int64_t)tile * S_TH + rr) * S_TW + 2 * lane;
-      if (base - 2 * lane >= n) break;
+    } else {
+      // RU rows' loads in flight together, then the rows in order
+      constexpr int RU = 4;
+      for (int r0 = 0; r0 < nrows; r0 += RU) {
+        double va[RU][2], vb[RU][2], vc[RU][2], vd[RU][2];
+        bool ok[RU][2];
+        int64_t ix[RU][2];
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int64_t i = base + v;
-        if (i >= n) continue;
-        switch (phase) {
-          case PH_INIT: {
-            const double bi = b[i];
-            r[i] = bi;
-            p[i] = bi;
-            x[i] = 0.0;
-            const double t = bi * bi;
-            acc = acc + t;
-          } break;
-          case PH_AXPY_DOT: {
-            const double t1 = alpha * p[i];
-            x[i] = x[i] + t1;
-            const double t2 = alpha * q[i];
-            const double ri = r[i] - t2;
-            r[i] = ri;
-            const double t = ri * ri;
-            acc = acc + t;
-          } break;
-          default: {
-            const double t = beta * p[i];
-            p[i] = t + r[i];
-          } break;
-        }
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int64_t i = t0 + (int64_t)(r0 + u) * S_TW + 2 * lane + v;
+            ix[u][v] = i;
+            ok[u][v] = r0 + u < nrows && i < n;
+            va[u][v] = vb[u][v] = vc[u][v] = vd[u][v] = 0.0;
+            if (!ok[u][v]) continue;
+            if (phase == PH_INIT) {
+              va[u][v] = b[i];
+            } else if (phase == PH_AXPY_DOT) {
+              va[u][v] = p[i];
+              vb[u][v] = x[i];
+              vc[u][v] = q[i];
+              vd[u][v] = r[i];
+            } else {
+              va[u][v] = p[i];
+              vb[u][v] = r[i];
+            }
+          }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            if (!ok[u][v]) continue;
+            const int64_t i = ix[u][v];
+            if (phase == PH_INIT) {
+              const double bi = va[u][v];
+              r[i] = bi;
+              p[i] = bi;
+              x[i] = 0.0;
+              const double t = bi * bi;
+              acc = acc + t;
+            } else if (phase == PH_AXPY_DOT) {
+              const double t1 = alpha * va[u][v];
+              x[i] = vb[u][v] + t1;
+              const double t2 = alpha * vc[u][v];
+              const double ri = vd[u][v] - t2;
+              r[i] = ri;
+              const double t = ri * ri;
+              acc = acc + t;
+            } else {
+              const double t = beta * va[u][v];
+              p[i] = t + vb[u][v];
+            }
+          }
       }
     }
     if (phase == PH_UPDATE_P) continue;
