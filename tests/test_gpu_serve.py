@@ -125,6 +125,9 @@ def test_admission_binds_to_budget():
 
 def test_error_paths():
     c = ctx()
+    with pytest.raises(B.DfxError) as e:
+        c.serve_start(hbm_budget=1 << 20, max_slots=2, tol=TOL, max_iter=7, iters_per_round=-1)
+    assert e.value.code == B.EINVAL
     c.serve_start(hbm_budget=1 << 20, max_slots=2, tol=TOL, max_iter=7)
     rp, col, val = synth.poisson_csr(200, 2)   # ~2.4 MB footprint
     with pytest.raises(B.DfxError) as e:
