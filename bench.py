@@ -34,7 +34,8 @@ def kernel_source_hash():
     for f in ("paper_2406_18109_amd/csrc/kernels.hip", "paper_2406_18109_amd/csrc/vm.h",
               "paper_2406_18109_amd/csrc/vm_exec.h", "paper_2406_18109_amd/csrc/dev_common.h",
               "paper_2406_18109_amd/csrc/vm_tier0.hip", "paper_2406_18109_amd/csrc/vm_tier1.hip",
-              "paper_2406_18109_amd/csrc/vm_tier2.hip", "paper_2406_18109_amd/csrc/vm_tier3.hip"):
+              "paper_2406_18109_amd/csrc/vm_tier2.hip", "paper_2406_18109_amd/csrc/vm_tier3.hip",
+              "paper_2406_18109_amd/csrc/dmath.h", "paper_2406_18109_amd/csrc/dmath_coef.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
