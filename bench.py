@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+# --tune: contexts time launch-shape candidates on each plan's first
+# executions (then every leg warms up for at least 8 executions)
+TUNE = False
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -74,7 +79,7 @@ class BSBench:
     def __init__(self, dfx, synth, wl, np, n, dtype, fuse):
         self.np = np
         npdt = np.float64 if dtype == "f64" else np.float32
-        self.ctx = dfx.Context(device=0, window_size=64, fuse=fuse)
+        self.ctx = dfx.Context(device=0, window_size=64, fuse=fuse, tune=TUNE)
         self.dfx, self.n, self.dtype = dfx, n, dtype
         S, K, T = synth.bs_inputs(n, npdt)
         r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL, npdt)
@@ -106,7 +111,7 @@ class BSBench:
 
 def bs_leg(torch, dfx, synth, wl, np, n, dtype, fuse, K, W):
     b = BSBench(dfx, synth, wl, np, n, dtype, fuse)
-    for _ in range(W):
+    for _ in range(max(W, 8) if TUNE else W):
         b.step()
     b.ctx.stats_reset()
     wall, ev = timed_steps(torch, b.ctx.torch_stream, b.step, K)
@@ -121,11 +126,11 @@ def bs_leg(torch, dfx, synth, wl, np, n, dtype, fuse, K, W):
 
 
 def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
-    c = dfx.Context(device=0, window_size=16, fuse=fuse)
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
     G = c.store_create([N, N], "f64")
     c.store_write(G, synth.jacobi_grid(N))
     J = dfx.apps.Jacobi(c, G, N)
-    for _ in range(3):
+    for _ in range(8 if TUNE else 3):
         J.sweep()
     c.sync()
     c.stats_reset()
@@ -143,7 +148,7 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
 
 
 def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
-    c = dfx.Context(device=0, window_size=16, fuse=fuse)
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
     rowptr, col, val = synth.poisson_csr(m, dim)
     n = m ** dim
     b = synth.rhs(n, synth.CG64_SEED if dim == 2 else synth.CG256_SEED)
@@ -154,7 +159,7 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
         hs.append(s)
     del rowptr, col, val
     cg = dfx.apps.CG(c, *hs, n)
-    for _ in range(2):
+    for _ in range(8 if TUNE else 2):
         cg.iteration()
     c.sync()
     g = None
@@ -234,7 +239,7 @@ def copy_leg(dfx, np, torch, n, K):
     """One COPY task over n doubles per step (reads and writes 8n bytes each):
     the streaming reference, and the known-size kernel that calibrates the
     HBM traffic counters."""
-    c = dfx.Context(device=0, window_size=4)
+    c = dfx.Context(device=0, window_size=4, tune=TUNE)
     a = c.store_create([n], "f64")
     c.store_write(a, np.zeros(n))
     b = c.store_create([n], "f64")
@@ -243,7 +248,7 @@ def copy_leg(dfx, np, torch, n, K):
     def step():
         c.submit("copy", [1], [(a, T, "R"), (b, T, "W")])
         c.flush()
-    for _ in range(2):
+    for _ in range(8 if TUNE else 2):
         step()
     wall, ev = timed_steps(torch, c.torch_stream, step, K)
     c.close()
@@ -272,6 +277,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tune", action="store_true",
+                    help="enable the library's launch-shape tuner (warm-ups extended to 8 executions)")
     ap.add_argument("--legs", default="all",
                     help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
@@ -280,6 +287,8 @@ def main():
                     help="CG iterations per scheduling round (0: the library default)")
     ap.add_argument("--log2n", type=int, default=26)
     args = ap.parse_args()
+    global TUNE
+    TUNE = args.tune
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the executor runs on "
               "a single device)" % args.gpus, file=sys.stderr)

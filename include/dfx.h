@@ -108,7 +108,12 @@ typedef struct {
   int32_t window_size;   /* tasks buffered before analysis runs (>= 1) */
   int32_t fuse;          /* 0: unfused baseline, one task per launch, every store materialised */
   int32_t memo;          /* 1: memoise analysis and plan on the window's canonical form */
-  int32_t reserved[9];
+  int32_t tune;          /* 1: a memoised pass times tiles-per-wave candidates (1x, 2x, 4x the
+                            default) on its first 7 executions and keeps the fastest (a
+                            candidate must beat the default by 3 %).  Results do not depend on
+                            the choice: every candidate keeps each block's tiles an aligned
+                            subtree of the reduction tree. */
+  int32_t reserved[8];
 } dfx_config;
 
 typedef struct {

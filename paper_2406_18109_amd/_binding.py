@@ -40,7 +40,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 class dfx_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
                 ("dealloc", FREE_FN), ("alloc_user", C.c_void_p), ("window_size", C.c_int32),
-                ("fuse", C.c_int32), ("memo", C.c_int32), ("reserved", C.c_int32 * 9)]
+                ("fuse", C.c_int32), ("memo", C.c_int32), ("tune", C.c_int32), ("reserved", C.c_int32 * 8)]
 
 
 class dfx_arg(C.Structure):
@@ -195,13 +195,14 @@ class Context:
     """One dfx context (dfx_create ... dfx_destroy)."""
 
     def __init__(self, device: int = 0, window_size: int = 16, fuse: bool = True, memo: bool = True,
-                 stream=None, allocator: str = "torch"):
+                 stream=None, allocator: str = "torch", tune: bool = False):
         self.L = lib()
         cfg = dfx_config()
         cfg.device = device
         cfg.window_size = window_size
         cfg.fuse = 1 if fuse else 0
         cfg.memo = 1 if memo else 0
+        cfg.tune = 1 if tune else 0
         self._alloc = None
         self.torch_stream = None
         if device >= 0:

@@ -650,6 +650,18 @@ static int trace_level() {
   return lvl;
 }
 
+
+// Launch shape of a pass for `tpw` tiles per wave (a power of two, so that
+// each block's tiles form an aligned subtree of the reduction tree): four
+// waves per block, the grid a multiple of 8 (one share per XCD) when large.
+static void set_shape(PassPlan& p, int64_t tpw) {
+  p.tiles_per_wave = tpw;
+  const int64_t waves = (p.n_tiles + tpw - 1) / tpw;
+  int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
+  if (grid > 8) grid = (grid + 7) / 8 * 8;
+  p.grid = (int)grid;
+}
+
 static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& tasks, const Space& sp,
                       int dtype, int kind, PassPlan& out) {
   const int tw = dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW;
@@ -969,12 +981,14 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   // lose bandwidth (measured on a plain copy: 5.5 TB/s with 32-row runs,
   // 5.0 with 64, 4.4 with 256).
   const int64_t target_waves = 32768;
-  out.tiles_per_wave = 1;
-  while (out.tiles_per_wave < VM_MAXTPW && out.tiles_per_wave * target_waves < out.n_tiles) out.tiles_per_wave *= 2;
-  const int64_t waves = (out.n_tiles + out.tiles_per_wave - 1) / out.tiles_per_wave;
-  int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
-  if (grid > 8) grid = (grid + 7) / 8 * 8;
-  out.grid = (int)grid;
+  int64_t tpw = 1;
+  while (tpw < VM_MAXTPW && tpw * target_waves < out.n_tiles) tpw *= 2;
+  set_shape(out, tpw);
+  // the tuner also times 2x and 4x the default (fewer, longer-running
+  // waves); small passes keep the default
+  out.tune_cand.clear();
+  if (c.cfg.tune && c.cfg.memo && !c.analysis_only && kind != 2 && out.n_tiles >= 64)
+    for (int64_t t = tpw; t <= VM_MAXTPW && t <= 4 * tpw; t *= 2) out.tune_cand.push_back(t);
   // algorithmic bytes: union footprint of every store read, and of every
   // store written, once per pass
   std::map<int64_t, std::vector<Box>> rd, wr;
@@ -1069,6 +1083,17 @@ static int ensure_workspace(Ctx& c, PassPlan& p) {
   return DFX_OK;
 }
 
+// Device resources a plan holds: reduction workspaces and tuner events.
+static void release_plan(Ctx& c, Plan& plan) {
+  for (auto& p : plan.passes) {
+    if (p.ws) dev_free(c, p.ws, p.ws_bytes);
+    p.ws = nullptr;
+    if (p.ev0) (void)hipEventDestroy(p.ev0);
+    if (p.ev1) (void)hipEventDestroy(p.ev1);
+    p.ev0 = p.ev1 = nullptr;
+  }
+}
+
 static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   auto S = [&](int cs) -> StoreRec& { return c.stores.at(order[cs]); };
   const size_t es = dtype_size(p.dtype);
@@ -1085,6 +1110,46 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   c.stats.alg_bytes += p.alg_bytes;
   if (c.capturing) { c.capture_launches += 1; c.capture_bytes += p.alg_bytes; }
   if (c.analysis_only) return DFX_OK;
+
+  // Launch-shape tuner.  A memoised pass runs once untimed (warm-up), then
+  // each candidate twice, interleaved, between two events; a timing is read
+  // at the plan's next execution, so tuning adds no synchronisation of its
+  // own.  A candidate replaces the default only if its faster run beats the
+  // default's by 3 %.  A graph being recorded takes the default shape.
+  bool timed = false;
+  if (!p.tune_cand.empty()) {
+    const int nc = (int)p.tune_cand.size();
+    if (p.tune_pending >= 0 && !c.capturing) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.ev1) == hipSuccess && hipEventElapsedTime(&ms, p.ev0, p.ev1) == hipSuccess)
+        p.tune_ms[p.tune_pending] = std::min(p.tune_ms[p.tune_pending], ms);
+      p.tune_pending = -1;
+    }
+    if (c.capturing) {
+      set_shape(p, p.tune_cand[0]);
+    } else if (p.tune_step > 2 * nc) {
+      int best = 0;
+      for (int k = 1; k < nc; ++k)
+        if (p.tune_ms[k] < p.tune_ms[best]) best = k;
+      if (p.tune_ms[best] > 0.97f * p.tune_ms[0]) best = 0;
+      set_shape(p, p.tune_cand[best]);
+      if (trace_level() > 0)
+        std::fprintf(stderr, "dfx: tuned pass kind=%d tiles=%lld tiles/wave=%lld (%.4f ms, default %.4f ms)\n",
+                     p.kind, (long long)p.n_tiles, (long long)p.tiles_per_wave, p.tune_ms[best], p.tune_ms[0]);
+      p.tune_cand.clear();
+    } else {
+      if (!p.ev0 && (hipEventCreate(&p.ev0) != hipSuccess || hipEventCreate(&p.ev1) != hipSuccess))
+        return fail(c, DFX_EHIP, "event creation failed");
+      if (p.tune_ms.size() != (size_t)nc) p.tune_ms.assign(nc, 3.0e38f);
+      const int k = p.tune_step == 0 ? 0 : (p.tune_step - 1) % nc;
+      set_shape(p, p.tune_cand[k]);
+      if (p.tune_step > 0) {
+        p.tune_pending = k;
+        timed = true;
+      }
+      p.tune_step += 1;
+    }
+  }
 
   VmParams P;
   std::memset(&P, 0, sizeof(P));
@@ -1156,8 +1221,10 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.sp_stage = st && (st[0] == '0' || st[0] == '1') ? st[0] == '1' : p.n_tiles >= 256;
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
+  if (timed) (void)hipEventRecord(p.ev0, c.stream);
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);
   if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
+  if (timed) (void)hipEventRecord(p.ev1, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
 }
@@ -1192,7 +1259,11 @@ static int dispatch_one(Ctx& c) {
     c.stats.memo_misses += 1;
     plan = owned.get();
     if (c.cfg.memo) {
-      if (c.memo.size() >= 4096) c.memo.clear();
+      if (c.memo.size() >= 4096) {
+        if (!c.analysis_only)
+          for (auto& kv : c.memo) release_plan(c, *kv.second);
+        c.memo.clear();
+      }
       c.memo.emplace(key, std::move(owned));
     }
   } else {
@@ -1200,8 +1271,13 @@ static int dispatch_one(Ctx& c) {
   }
   for (auto& p : plan->passes) {
     int rc = run_pass(c, p, order);
-    if (rc) return rc;
+    if (rc) {
+      if (owned && !c.analysis_only) release_plan(c, *owned);
+      return rc;
+    }
   }
+  // an unmemoised plan is used once (its workspace is freed in stream order)
+  if (owned && !c.analysis_only) release_plan(c, *owned);
   // record the group
   dfx_group_info gi;
   std::memset(&gi, 0, sizeof(gi));
@@ -1285,9 +1361,7 @@ int dfx_destroy(dfx_ctx* c) {
   if (c->server) (void)dfx_serve_stop(c);
   int rc = c->capturing ? DFX_OK : flush(*c);
   if (!c->analysis_only) {
-    for (auto& kv : c->memo)
-      for (auto& p : kv.second->passes)
-        if (p.ws) dev_free(*c, p.ws, p.ws_bytes);
+    for (auto& kv : c->memo) release_plan(*c, *kv.second);
     for (auto& kv : c->stores)
       if (kv.second.ptr && !kv.second.external) dev_free(*c, kv.second.ptr, kv.second.bytes);
     for (auto& g : c->graphs) {

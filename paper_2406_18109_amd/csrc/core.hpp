@@ -109,6 +109,13 @@ struct PassPlan {
   // per-plan device workspace: one reduction subtree sum per block
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // launch-shape tuner: tiles-per-wave candidates timed on the plan's first
+  // executions (empty once the choice is fixed, or when tuning is off)
+  std::vector<int64_t> tune_cand;   // candidate 0 is the default shape
+  std::vector<float> tune_ms;       // fastest timing per candidate
+  int tune_step = 0;          // execution count while tuning (0: the untimed warm-up)
+  int tune_pending = -1;      // candidate whose events are in flight
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 struct Plan {
