@@ -275,8 +275,8 @@ def cpu_baseline(synth, wl, np, sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tune", action="store_true",
                     help="enable the library's launch-shape tuner (warm-ups extended to 8 executions)")
     ap.add_argument("--legs", default="all",
