@@ -1083,6 +1083,33 @@ static int ensure_workspace(Ctx& c, PassPlan& p) {
   return DFX_OK;
 }
 
+// Rows per step of an arithmetic pass: one (four waves per SIMD) when the
+// default two-row kernel could not hold all of the pass's waves at once but
+// the one-row kernel can, so the pass runs in one round instead of leaving a
+// partial second one (a 4096-tile pass at three waves per SIMD, for one).
+// Passes of many rounds keep two rows per step, which streams better.
+// (DFX_ARITH_ROWS=1 or 2 overrides the choice.)
+static int pick_rows(Ctx& c, const PassPlan& p) {
+  if (p.tier != TIER_ARITH || p.kind != 0) return 0;
+  const char* env = std::getenv("DFX_ARITH_ROWS");
+  if (env && (env[0] == '1' || env[0] == '2')) return env[0] == '1' ? 1 : 0;
+  const int64_t waves = (p.n_tiles + p.tiles_per_wave - 1) / p.tiles_per_wave;
+  const int f64 = p.dtype == DFX_F64;
+  const int nin = (int)p.ins.size();
+  const int bi = stream_bucket(nin, TIER_ARITH) / 2 - 1;
+  if (!c.n_cu) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c.cfg.device) != hipSuccess || v < 1) v = 1;
+    c.n_cu = v;
+  }
+  auto resident = [&](int rows) -> int64_t {
+    int& w = c.waves_cu[f64][bi][rows];
+    if (!w) w = std::max(1, arith_waves_per_cu(f64, nin, rows));
+    return (int64_t)w * c.n_cu;
+  };
+  return waves > resident(0) && waves <= resident(1) ? 1 : 0;
+}
+
 // Device resources a plan holds: reduction workspaces and tuner events.
 static void release_plan(Ctx& c, Plan& plan) {
   for (auto& p : plan.passes) {
@@ -1222,7 +1249,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
-  int e = launch_vm(P, p.dtype == DFX_F64, p.tier, c.stream);
+  int e = launch_vm(P, p.dtype == DFX_F64, p.tier, pick_rows(c, p), c.stream);
   if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
   if (timed) (void)hipEventRecord(p.ev1, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));

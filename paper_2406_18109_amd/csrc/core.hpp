@@ -14,7 +14,8 @@
 
 namespace dfx {
 
-int launch_vm(const VmParams& P, int is_f64, int tier, hipStream_t stream);
+int launch_vm(const VmParams& P, int is_f64, int tier, int rows, hipStream_t stream);
+int arith_waves_per_cu(int is_f64, int n_in, int rows);
 int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream);
 int stream_bucket(int n_in, int tier);
 
@@ -157,6 +158,9 @@ struct Ctx {
 
   dfx_stats stats{};
   void* server = nullptr;   // continuous-batching CG server, if started
+  // resident waves of the arithmetic kernels: [f64][stream bucket 2/4/6][rows 1]
+  int n_cu = 0;
+  int waves_cu[2][3][2] = {};
 };
 
 }  // namespace dfx

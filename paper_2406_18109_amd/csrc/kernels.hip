@@ -9,7 +9,8 @@
 
 namespace dfx {
 
-int launch_vm_tier0(const VmParams& P, int is_f64, int nb, hipStream_t stream);
+int launch_vm_tier0(const VmParams& P, int is_f64, int nb, int rows, hipStream_t stream);
+int vm_tier0_waves_per_cu(int is_f64, int nb, int rows);
 int launch_vm_tier1(const VmParams& P, int is_f64, int nb, hipStream_t stream);
 int launch_vm_tier2(const VmParams& P, int is_f64, int nb, hipStream_t stream);
 int launch_vm_tier3(const VmParams& P, int is_f64, int nb, hipStream_t stream);
@@ -60,12 +61,19 @@ int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream) {
 
 int stream_bucket(int n_in, int tier) { return tier == TIER_POW ? VM_MAXIN : n_in <= 2 ? 2 : n_in <= 4 ? 4 : 6; }
 
-// Host-side launch; returns the hipError_t of the launch.
-int launch_vm(const VmParams& P, int is_f64, int tier, hipStream_t stream) {
+// Waves per compute unit of the tier-0 (arithmetic, non-SpMV) kernel for
+// `n_in` streams with one row per step (rows 1) or the default.
+int arith_waves_per_cu(int is_f64, int n_in, int rows) {
+  return vm_tier0_waves_per_cu(is_f64, stream_bucket(n_in, TIER_ARITH), rows);
+}
+
+// Host-side launch; returns the hipError_t of the launch.  `rows` 1 selects
+// the one-row arithmetic kernels (tier 0, non-SpMV passes).
+int launch_vm(const VmParams& P, int is_f64, int tier, int rows, hipStream_t stream) {
   const int nb = stream_bucket(P.n_in, tier);
   if (P.n_in > nb) return (int)hipErrorInvalidValue;
   switch (tier) {
-    case TIER_ARITH: return launch_vm_tier0(P, is_f64, nb, stream);
+    case TIER_ARITH: return launch_vm_tier0(P, is_f64, nb, P.spmv ? 0 : rows, stream);
     case TIER_TRANS8: return launch_vm_tier1(P, is_f64, nb, stream);
     case TIER_TRANS16: return launch_vm_tier2(P, is_f64, nb, stream);
     default: return launch_vm_tier3(P, is_f64, nb, stream);

@@ -52,7 +52,9 @@ template <typename T> __device__ __forceinline__ T d_abs(T x) { return x < (T)0 
 #define DFX_ARITH_F64_GS 1
 #endif
 
-template <typename T, int HV, bool SPMV, int NR_> struct Shape {
+// ROWS > 0 fixes the rows per step (the one-row arithmetic kernels, which
+// fit four waves per SIMD); 0 takes the rule below.
+template <typename T, int HV, bool SPMV, int NR_, int ROWS = 0> struct Shape {
   static constexpr bool HEAVY = HV > 0;
   static constexpr int V = Lanes<T>::V;
   static constexpr int TW = Lanes<T>::TW;
@@ -63,6 +65,7 @@ template <typename T, int HV, bool SPMV, int NR_> struct Shape {
   // depend on U.
   static constexpr int FIT = 256 / (NR * V * (int)sizeof(T));
   static constexpr int U = SPMV ? 1
+                         : ROWS > 0 ? ROWS
                          : (HEAVY && NR == VM_NREG_LIGHT && sizeof(T) == 8) ? DFX_TRANS8_F64_ROWS
                          : (HEAVY && NR == VM_NREG_LIGHT) ? DFX_TRANS8_F32_ROWS
                          : (FIT >= 2 ? 2 : 1);
@@ -287,17 +290,17 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
 // step (row next_row0, known to be MODE_FAST) are issued into L as soon as
 // this step's values are in registers, so they are in flight during the op
 // list and the stores.
-template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT>
+template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS>
 __device__ __forceinline__ void vm_step(
     const VmParams& P,
-    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R0)[NR],
-    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R1)[NR],
-    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R2)[NR],
-    typename GVec<T, Shape<T, HV, SPMV, NR>::GS>::type (&R3)[NR],
-    VmState<T, Shape<T, HV, SPMV, NR>::NG, Shape<T, HV, SPMV, NR>::GS>& G,
-    T (&L)[NINB][Shape<T, HV, SPMV, NR>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R1)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R2)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R3)[NR],
+    VmState<T, Shape<T, HV, SPMV, NR, ROWS>::NG, Shape<T, HV, SPMV, NR, ROWS>::GS>& G,
+    T (&L)[NINB][Shape<T, HV, SPMV, NR, ROWS>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
     const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval) {
-  typedef Shape<T, HV, SPMV, NR> S;
+  typedef Shape<T, HV, SPMV, NR, ROWS> S;
   constexpr bool HEAVY = S::HEAVY;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
   static_assert(NINB <= NR, "stream bucket exceeds the register file");
@@ -558,10 +561,10 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
 #ifndef DFX_SPMV_WAVES
 #define DFX_SPMV_WAVES 4
 #endif
-template <typename T, int HV, bool SPMV, int NR, int NINB>
+template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SPMV && HV == 0 ? DFX_SPMV_WAVES : 1)))
 void vm_kernel(const VmParams P) {
-  typedef Shape<T, HV, SPMV, NR> S;
+  typedef Shape<T, HV, SPMV, NR, ROWS> S;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
   typedef typename GVec<T, GS>::type gvec;
   __shared__ T tsum[VM_MAXRED][4 * VM_MAXTPW];  // this block's tile sums
@@ -643,7 +646,7 @@ void vm_kernel(const VmParams P) {
         next_fast = r + U < RED_TH && P.unit_cols &&
                     (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
       }
-      vm_step<T, HV, SPMV, NR, NINB, SPLIT>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U,
+      vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U,
                                             sp_col[SPMV ? wib : 0], sp_val[SPMV ? wib : 0]);
       have = next_fast;
     }
@@ -672,23 +675,46 @@ void vm_kernel(const VmParams P) {
 
 // Launch one pass on a tier's kernels: element type, SpMV prologue and
 // stream bucket select the instantiation.
-template <int HV, int NR, int NB0, int NB1, int NB2>
+template <int HV, int NR, int NB0, int NB1, int NB2, int ROWS = 0>
 int launch_tier(const VmParams& P, int is_f64, int nb, hipStream_t st) {
   const dim3 g(P.grid), b(BLOCK);
   const bool sp = P.spmv != 0;
 #define DFX_L(T, SP)                                                                              \
   {                                                                                               \
-    if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0>), g, b, 0, st, P);           \
-    else if (nb == NB1) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB1>), g, b, 0, st, P);      \
-    else hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB2>), g, b, 0, st, P);                     \
+    if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0, ROWS>), g, b, 0, st, P);     \
+    else if (nb == NB1) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB1, ROWS>), g, b, 0, st, P); \
+    else hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB2, ROWS>), g, b, 0, st, P);               \
   }
-  if (is_f64) {
-    if (sp) DFX_L(double, true) else DFX_L(double, false)
+  if constexpr (ROWS > 0) {
+    if (sp) return (int)hipErrorInvalidValue;   // SpMV steps take one row in every variant
+    if (is_f64) DFX_L(double, false) else DFX_L(float, false)
   } else {
-    if (sp) DFX_L(float, true) else DFX_L(float, false)
+    if (is_f64) {
+      if (sp) DFX_L(double, true) else DFX_L(double, false)
+    } else {
+      if (sp) DFX_L(float, true) else DFX_L(float, false)
+    }
   }
 #undef DFX_L
   return (int)hipGetLastError();
+}
+
+// Waves of one non-SpMV kernel of a tier that one compute unit holds at once
+// (its occupancy), from the runtime's occupancy calculator.
+template <int HV, int NR, int NB0, int NB1, int NB2, int ROWS = 0>
+int tier_waves_per_cu(int is_f64, int nb) {
+  int blocks = 0;
+  const void* f = nullptr;
+  if (is_f64)
+    f = nb == NB0 ? (const void*)&vm_kernel<double, HV, false, NR, NB0, ROWS>
+      : nb == NB1 ? (const void*)&vm_kernel<double, HV, false, NR, NB1, ROWS>
+                  : (const void*)&vm_kernel<double, HV, false, NR, NB2, ROWS>;
+  else
+    f = nb == NB0 ? (const void*)&vm_kernel<float, HV, false, NR, NB0, ROWS>
+      : nb == NB1 ? (const void*)&vm_kernel<float, HV, false, NR, NB1, ROWS>
+                  : (const void*)&vm_kernel<float, HV, false, NR, NB2, ROWS>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, BLOCK, 0) != hipSuccess) return 0;
+  return blocks * (BLOCK / WAVE);
 }
 
 }  // namespace dfx

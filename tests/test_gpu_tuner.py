@@ -85,3 +85,17 @@ def test_tuned_cg_bit_identical():
     note("tuner: cg 3-D m=%d" % m)
     (r1, x1), (r0, x0) = _cg(True, m), _cg(False, m)
     assert r1 == r0 and np.array_equal(x1, x0)
+
+
+@pytest.mark.parametrize("rows", ["1", "2"])
+def test_rows_per_step_bit_identical(rows, monkeypatch):
+    """Arithmetic passes of 4096 tiles take the one-row kernels (all waves
+    resident at four per SIMD); forcing one or two rows per step gives the
+    same bits, since rows are visited in order either way."""
+    n = 4096 * 4096 - 5   # 4096 tiles, ragged tail
+    note("rows per step: auto against %s, n=%d" % (rows, n))
+    auto = _reductions(False, n)
+    monkeypatch.setenv("DFX_ARITH_ROWS", rows)
+    forced = _reductions(False, n)
+    for (s1, d1, z1), (s0, d0, z0) in zip(forced, auto):
+        assert s1 == s0 and d1 == d0 and np.array_equal(z1, z0)
