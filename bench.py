@@ -9,8 +9,10 @@ group executed as one kernel.  Inputs are resident in HBM before timing.
 Printed: one JSON line with the headline (fused algorithmic HBM GB/s), the
 roofline of the dominant kernel, the CPU oracle timed on a bounded sample,
 and the other legs of the metric (unfused GB/s, FP32, Jacobi stencil, CG
-iterations/s, and the continuous-batching server's solves/s with p50/p99
-latency over the 4096-request stream) under "legs".  Progress goes to stderr.
+iterations/s, and the continuous-batching server: its closed-loop saturation
+solves/s, then p50/p99 latency with Poisson arrivals at 0.5, 0.8 and 0.95 of
+saturation, the 0.8 point over the whole 4096-request stream) under "legs".
+Progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -188,14 +190,16 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
     return out
 
 
-def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0):
+def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0, mats=None):
     """Continuous-batching server on the first `count` requests of the serving
     stream: 2-D Poisson solves, side uniform in [32, 512], tol 1e-8, Poisson
-    arrivals at `rate` per second.  Latency = completion - arrival."""
+    arrivals at `rate` per second (None: every request submitted at once, the
+    closed-loop saturation run).  Latency = completion - arrival."""
     import threading
     sides = synth.serve_sides(count)
-    arrivals = synth.serve_arrivals(count, rate)
-    mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
+    arrivals = np.zeros(count) if rate is None else synth.serve_arrivals(count, rate)
+    if mats is None:
+        mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
     c = dfx.Context(device=0)
     c.serve_start(hbm_budget=budget, max_slots=slots, tol=1e-8, max_iter=20000, iters_per_round=ipr)
     tickets = [None] * count
@@ -235,6 +239,33 @@ def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0):
             "peak_bytes": st["peak_bytes"], "hbm_budget": budget, "max_slots": slots, "wall_s": wall}
 
 
+SERVE_LOADS = (0.5, 0.8, 0.95)
+
+
+def serve_sweep(dfx, synth, np, count, budget, slots, ipr=0):
+    """Saturation throughput from a closed-loop run (all requests at once),
+    then Poisson arrivals at 0.5, 0.8 and 0.95 of it; the leg's p50/p99 are
+    those at 0.8, over the whole stream.  The saturation run and the 0.5 and
+    0.95 points use the stream's first 1024 requests (GPU time)."""
+    sides = synth.serve_sides(count)
+    mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
+    short = min(count, 1024)
+    log("serve: closed loop, %d requests" % short)
+    sat = serve_leg(dfx, synth, np, short, None, budget, slots, ipr, mats)
+    out = {"saturation_solves_per_s": sat["solves_per_s"], "closed_loop": sat, "loads": {}}
+    for f in SERVE_LOADS:
+        rate = f * sat["solves_per_s"]
+        n = count if f == 0.8 else short
+        log("serve: %d requests, arrivals at %.2f of saturation (%.1f/s)" % (n, f, rate))
+        out["loads"]["%.2f" % f] = serve_leg(dfx, synth, np, n, rate, budget, slots, ipr, mats)
+    main = out["loads"]["0.80"]
+    for k in ("requests", "converged", "arrival_rate_per_s", "solves_per_s", "p50_latency_s", "p99_latency_s",
+              "mean_iterations", "hbm_budget", "max_slots", "peak_bytes"):
+        out[k] = main[k]
+    out["load"] = 0.8
+    return out
+
+
 def copy_leg(dfx, np, torch, n, K):
     """One COPY task over n doubles per step (reads and writes 8n bytes each):
     the streaming reference, and the known-size kernel that calibrates the
@@ -272,6 +303,14 @@ def cpu_baseline(synth, wl, np, sample):
     return sample * 40 / dt / 1e9, reps, dt
 
 
+def serve_main(dfx, synth, np, args):
+    budget = int(args.serve_budget_gb * (1 << 30))
+    if args.serve_rate is None:
+        return serve_sweep(dfx, synth, np, args.serve_requests, budget, args.serve_slots, args.serve_iters_per_round)
+    return serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, budget, args.serve_slots,
+                     args.serve_iters_per_round)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,7 +321,10 @@ def main():
     ap.add_argument("--legs", default="all",
                     help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
-    ap.add_argument("--serve-rate", type=float, default=120.0)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="fixed Poisson arrival rate; default: a saturation run, then 0.5/0.8/0.95 of it")
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-iters-per-round", type=int, default=0,
                     help="CG iterations per scheduling round (0: the library default)")
     ap.add_argument("--log2n", type=int, default=26)
@@ -307,7 +349,7 @@ def main():
         print(json.dumps(copy_leg(dfx, np, torch, n, K)))
         return
     if args.legs == "serve":
-        out = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64, args.serve_iters_per_round)
+        out = serve_main(dfx, synth, np, args)
         print(json.dumps(out))
         return
     # legs: "all" (the default line), "headline", or a comma-separated list of
@@ -349,8 +391,7 @@ def main():
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
     if "serve" in sel:
         log("serving: %d CG solves, Poisson arrivals at %.0f/s" % (args.serve_requests, args.serve_rate))
-        legs["serve"] = serve_leg(dfx, synth, np, args.serve_requests, args.serve_rate, 16 << 30, 64,
-                                  args.serve_iters_per_round)
+        legs["serve"] = serve_main(dfx, synth, np, args)
 
     log("cpu oracle sample")
     sample = 1 << 21
