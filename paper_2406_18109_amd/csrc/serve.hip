@@ -17,7 +17,15 @@ namespace dfx {
 
 constexpr int S_TW = 128;   // FP64 row width of the canonical tiling
 constexpr int S_TH = RED_TH;
+// tile rows whose SpMV groups one csr_rows call walks together
+#ifndef DFX_SERVE_SPMV_ROWS
+#define DFX_SERVE_SPMV_ROWS 2
+#endif
+constexpr int SR = DFX_SERVE_SPMV_ROWS;
 
+// One instantiation per phase, so the elementwise phases do not carry the
+// SpMV phase's registers (and keep more waves per SIMD).
+template <int PHASE>
 __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L) {
   const int lane = threadIdx.x & (WAVE - 1);
   int lb = blockIdx.x;
@@ -25,7 +33,7 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
   const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t i0 = gw * L.items_per_wave;
   const int64_t i1 = min(i0 + L.items_per_wave, L.n_items);
-  const int phase = L.phase;
+  constexpr int phase = PHASE;
 
   for (int64_t it = i0; it < i1; ++it) {
     const int slot = L.item_slot[it];
@@ -48,28 +56,28 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
       // four 64-row groups, per call), then p.q in the canonical order (lane
       // l owns elements 2l, 2l+1 of each row)
       const int32_t nnz = S->rowptr[n];
-      for (int r0 = 0; r0 < nrows; r0 += 2) {
-        int64_t gi[4];
-        bool gok[4];
-        double y[4], pv[2][2];
+      for (int r0 = 0; r0 < nrows; r0 += SR) {
+        int64_t gi[2 * SR];
+        bool gok[2 * SR];
+        double y[2 * SR], pv[SR][2];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 2 * SR; ++m) {
           gi[m] = t0 + (int64_t)(r0 + m / 2) * S_TW + (m % 2) * WAVE + lane;
           gok[m] = r0 + m / 2 < nrows && gi[m] < n;
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < SR; ++h)
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             const int64_t i = t0 + (int64_t)(r0 + h) * S_TW + 2 * lane + v;
             pv[h][v] = r0 + h < nrows && i < n ? p[i] : 0.0;
           }
-        csr_rows<double, 4>(S->rowptr, S->col, S->val, p, gi, gok, nnz, (uint32_t)n, y);
+        csr_rows<double, 2 * SR>(S->rowptr, S->col, S->val, p, gi, gok, nnz, (uint32_t)n, y);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2 * SR; ++m)
           if (gok[m]) q[gi[m]] = y[m];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < SR; ++h) {
           if (r0 + h >= nrows) break;
           const double yy[2] = {y[2 * h], y[2 * h + 1]};
           double qo[4];
@@ -179,7 +187,12 @@ __global__ __launch_bounds__(BLOCK) void serve_final_kernel(SolveDev* solves, co
 }
 
 int launch_serve_phase(const ServeLaunch& L, hipStream_t stream) {
-  hipLaunchKernelGGL(serve_phase_kernel, dim3(L.grid), dim3(BLOCK), 0, stream, L);
+  switch (L.phase) {
+    case PH_INIT: hipLaunchKernelGGL(serve_phase_kernel<PH_INIT>, dim3(L.grid), dim3(BLOCK), 0, stream, L); break;
+    case PH_SPMV_DOT: hipLaunchKernelGGL(serve_phase_kernel<PH_SPMV_DOT>, dim3(L.grid), dim3(BLOCK), 0, stream, L); break;
+    case PH_AXPY_DOT: hipLaunchKernelGGL(serve_phase_kernel<PH_AXPY_DOT>, dim3(L.grid), dim3(BLOCK), 0, stream, L); break;
+    default: hipLaunchKernelGGL(serve_phase_kernel<PH_UPDATE_P>, dim3(L.grid), dim3(BLOCK), 0, stream, L); break;
+  }
   if (L.phase != PH_UPDATE_P && L.n_fin > 0)
     hipLaunchKernelGGL(serve_final_kernel, dim3(L.n_fin), dim3(BLOCK), 0, stream, L.solves, L.fin_slots, L.phase);
   return (int)hipGetLastError();
