@@ -390,7 +390,8 @@ def main():
         legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
     if "serve" in sel:
-        log("serving: %d CG solves, Poisson arrivals at %.0f/s" % (args.serve_requests, args.serve_rate))
+        log("serving: %d CG solves, %s" % (args.serve_requests, "load sweep" if args.serve_rate is None
+                                              else "Poisson arrivals at %.0f/s" % args.serve_rate))
         legs["serve"] = serve_main(dfx, synth, np, args)
 
     log("cpu oracle sample")
