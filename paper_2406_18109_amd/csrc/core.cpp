@@ -1287,7 +1287,10 @@ static int dispatch_one(Ctx& c) {
     plan = owned.get();
     if (c.cfg.memo) {
       if (c.memo.size() >= 4096) {
-        if (!c.analysis_only)
+        // a recorded graph keeps using the workspaces of the plans it ran, so
+        // they are returned only while no graph exists
+        const bool graphs_live = std::any_of(c.graphs.begin(), c.graphs.end(), [](const auto& g) { return (bool)g; });
+        if (!c.analysis_only && !graphs_live && !c.capturing)
           for (auto& kv : c.memo) release_plan(c, *kv.second);
         c.memo.clear();
       }
@@ -1299,12 +1302,13 @@ static int dispatch_one(Ctx& c) {
   for (auto& p : plan->passes) {
     int rc = run_pass(c, p, order);
     if (rc) {
-      if (owned && !c.analysis_only) release_plan(c, *owned);
+      if (owned && !c.analysis_only && !c.capturing) release_plan(c, *owned);
       return rc;
     }
   }
-  // an unmemoised plan is used once (its workspace is freed in stream order)
-  if (owned && !c.analysis_only) release_plan(c, *owned);
+  // an unmemoised plan is used once (its workspace is freed in stream order),
+  // unless a graph being recorded refers to it
+  if (owned && !c.analysis_only && !c.capturing) release_plan(c, *owned);
   // record the group
   dfx_group_info gi;
   std::memset(&gi, 0, sizeof(gi));
