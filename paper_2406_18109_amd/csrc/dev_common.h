@@ -106,6 +106,97 @@ __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ rowptr, con
   }
 }
 
+// Row g0 + lane of a 64-row group (0 past n), with the group's contiguous
+// CSR range staged in this wave's LDS slice (scol, sval: SP_CAP entries) by
+// coalesced 16-byte nontemporal loads, so every line of col and val is
+// fetched once and does not displace x in L2; each lane then walks its row
+// from LDS.  A range longer than SP_CAP is read directly (csr_row).  Either
+// way the row is summed sequentially in CSR order.  Every lane of the wave
+// calls it.
+constexpr int SP_CAP = 512;
+
+template <typename T>
+__device__ __forceinline__ T csr_group(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                       const T* __restrict__ val, const T* __restrict__ x, int64_t g0, int64_t n,
+                                       int32_t nnz, uint32_t nx, int32_t* __restrict__ scol, T* __restrict__ sval) {
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  typedef T vv __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int VE = 16 / sizeof(T);   // values per 16-byte load
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t i = g0 + lane;
+  // the group's range from the lanes' own row pointers (first row, last valid row)
+  const int last = (int)(min(g0 + WAVE, n) - g0) - 1;
+  const int32_t rb_raw = i < n ? rowptr[i] : 0;
+  const int32_t re_raw = i < n ? rowptr[i + 1] : 0;
+  const int32_t nb = min(max(__builtin_amdgcn_readfirstlane(rb_raw), 0), nnz);
+  const int32_t ne = min(max(__builtin_amdgcn_readlane(re_raw, last), nb), nnz);
+  const int32_t a0 = nb & ~3;
+  const int32_t cnt = ne - a0;
+  if (cnt > SP_CAP) return i < n ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
+  // stage [a0, ne) of col and val: every chunk's load is in flight before
+  // the first LDS store (cnt <= SP_CAP here)
+  constexpr int CC = SP_CAP / (4 * WAVE), VC = SP_CAP / (VE * WAVE);
+  i4 cb[CC];
+  vv vb[VC];
+#pragma unroll
+  for (int u = 0; u < CC; ++u) {
+    const int j = (u * WAVE + lane) * 4;
+    if (j < cnt) {
+      if (a0 + j + 3 < nnz) cb[u] = __builtin_nontemporal_load((const i4*)(colidx + a0 + j));
+      else
+        for (int t = 0; t < 4; ++t) cb[u][t] = a0 + j + t < nnz ? colidx[a0 + j + t] : 0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < VC; ++u) {
+    const int j = (u * WAVE + lane) * VE;
+    if (j < cnt) {
+      if (a0 + j + VE - 1 < nnz) vb[u] = __builtin_nontemporal_load((const vv*)(val + a0 + j));
+      else
+        for (int t = 0; t < VE; ++t) vb[u][t] = a0 + j + t < nnz ? val[a0 + j + t] : (T)0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CC; ++u) {
+    const int j = (u * WAVE + lane) * 4;
+    if (j < cnt) *(i4*)(scol + j) = cb[u];
+  }
+#pragma unroll
+  for (int u = 0; u < VC; ++u) {
+    const int j = (u * WAVE + lane) * VE;
+    if (j < cnt) *(vv*)(sval + j) = vb[u];
+  }
+  __builtin_amdgcn_wave_barrier();
+  T sm = (T)0;
+  if (i < n) {
+    // clamped into the staged window: a malformed rowptr reads wrong values, never outside it
+    const int32_t rb = min(max(rb_raw, nb), ne);
+    const int32_t re = min(max(re_raw, rb), ne);
+    const int32_t b = rb - a0, e = re - a0;
+    for (int32_t k = b; k < e; k += 8) {
+      int32_t c[8];
+      T av[8], xv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int32_t kk = k + t < e ? k + t : b;
+        c[t] = scol[kk];
+        av[t] = sval[kk];
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) xv[t] = x[(uint32_t)c[t] < nx ? c[t] : 0];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (k + t < e) {
+          const T tv = av[t] * xv[t];
+          sm = (k + t == b) ? tv : sm + tv;
+        }
+    }
+  }
+  // every lane's reads of this group are done before the next group is staged
+  __builtin_amdgcn_wave_barrier();
+  return sm;
+}
+
 // Move per-lane row results to the canonical owners: y[m] of lane l holds the
 // element 64m + l of a run of V*64 elements; lane l receives elements V*l + v
 // (v < V) in out[v].

@@ -22,6 +22,10 @@ constexpr int S_TH = RED_TH;
 #define DFX_SERVE_SPMV_ROWS 2
 #endif
 constexpr int SR = DFX_SERVE_SPMV_ROWS;
+// 1: the SpMV phase stages each 64-row group's CSR range in LDS (csr_group)
+#ifndef DFX_SERVE_SPMV_STAGE
+#define DFX_SERVE_SPMV_STAGE 0
+#endif
 
 // One instantiation per phase, so the elementwise phases do not carry the
 // SpMV phase's registers (and keep more waves per SIMD).
@@ -51,7 +55,36 @@ __global__ __launch_bounds__(BLOCK) void serve_phase_kernel(const ServeLaunch L)
     const int64_t t0 = (int64_t)tile * S_TH * S_TW;
     const int nrows = (int)min((int64_t)S_TH, (n - t0 + S_TW - 1) / S_TW);  // rows of the tile inside n
     double acc = 0.0;
-    if (phase == PH_SPMV_DOT) {
+    if constexpr (phase == PH_SPMV_DOT && DFX_SERVE_SPMV_STAGE) {
+      // q = A p, one 64-row group at a time with its CSR range staged in
+      // LDS, then p.q in the canonical order (lane l owns elements 2l, 2l+1
+      // of each row)
+      __shared__ int32_t sp_col[BLOCK / WAVE][SP_CAP];
+      __shared__ double sp_val[BLOCK / WAVE][SP_CAP];
+      const int wib = threadIdx.x / WAVE;
+      const int32_t nnz = S->rowptr[n];
+      for (int rr = 0; rr < nrows; ++rr) {
+        const int64_t rb = t0 + (int64_t)rr * S_TW;
+        double y[2], pv[2], qo[4];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) pv[v] = rb + 2 * lane + v < n ? p[rb + 2 * lane + v] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int64_t g0 = rb + m * WAVE;
+          y[m] = g0 < n ? csr_group<double>(S->rowptr, S->col, S->val, p, g0, n, nnz, (uint32_t)n, sp_col[wib],
+                                            sp_val[wib])
+                        : 0.0;
+          if (g0 + lane < n) q[g0 + lane] = y[m];
+        }
+        rows_to_owners<double, 2>(y, qo);
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          if (rb + 2 * lane + v < n) {
+            const double t = pv[v] * qo[v];
+            acc = acc + t;
+          }
+      }
+    } else if constexpr (phase == PH_SPMV_DOT) {
       // q = A p with consecutive rows on consecutive lanes (two tile rows,
       // four 64-row groups, per call), then p.q in the canonical order (lane
       // l owns elements 2l, 2l+1 of each row)

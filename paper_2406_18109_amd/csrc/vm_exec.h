@@ -136,14 +136,10 @@ enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
 // y = A x for the V*64 elements of a step starting at element `base`.  The
 // row of element base + 64m + l is computed by lane l (consecutive rows on
 // consecutive lanes), then handed to its owner in the canonical layout by
-// shuffles.  Each group of 64 rows reads a contiguous CSR range; when it fits
-// SP_CAP entries the wave stages that range in LDS with coalesced 16-byte
-// nontemporal loads (every line of col and val is fetched once and does not
-// displace x in L2), and each lane walks its row from LDS.  Longer ranges read
-// CSR directly (csr_row).  Either way a row is summed sequentially in CSR
-// order, so the result does not depend on the path.
-constexpr int SP_CAP = 512;
-
+// shuffles.  With sp_stage each 64-row group goes through csr_group (its CSR
+// range staged in LDS); without, each lane reads its row directly (csr_row).
+// Either way a row is summed sequentially in CSR order, so the result does
+// not depend on the path.
 template <typename T, int V>
 __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&out)[4], int32_t* __restrict__ scol,
                                           T* __restrict__ sval) {
@@ -154,9 +150,6 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
   const T* __restrict__ x = (const T*)P.x;
   const int32_t nnz = P.nnz;
   const uint32_t nx = (uint32_t)P.nx;
-  typedef int32_t i4 __attribute__((ext_vector_type(4)));
-  typedef T vv __attribute__((ext_vector_type(16 / sizeof(T))));
-  constexpr int VE = 16 / sizeof(T);   // values per 16-byte load
   T y[V];
 #pragma unroll
   for (int m = 0; m < V; ++m) {
@@ -167,80 +160,7 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
       y[m] = i < P.n1d ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
       continue;
     }
-    // the group's range from the lanes' own row pointers (first row, last valid row)
-    const int last = (int)(min(g0 + WAVE, P.n1d) - g0) - 1;
-    const int32_t rb_raw = i < P.n1d ? rowptr[i] : 0;
-    const int32_t re_raw = i < P.n1d ? rowptr[i + 1] : 0;
-    const int32_t nb = min(max(__builtin_amdgcn_readfirstlane(rb_raw), 0), nnz);
-    const int32_t ne = min(max(__builtin_amdgcn_readlane(re_raw, last), nb), nnz);
-    const int32_t a0 = nb & ~3;
-    const int32_t cnt = ne - a0;
-    if (cnt > SP_CAP) {
-      y[m] = i < P.n1d ? csr_row<T>(rowptr, colidx, val, x, i, nnz, nx) : (T)0;
-      continue;
-    }
-    // stage [a0, ne) of col and val: every chunk's load is in flight before
-    // the first LDS store (cnt <= SP_CAP here)
-    constexpr int CC = SP_CAP / (4 * WAVE), VC = SP_CAP / (VE * WAVE);
-    i4 cb[CC];
-    vv vb[VC];
-#pragma unroll
-    for (int u = 0; u < CC; ++u) {
-      const int j = (u * WAVE + lane) * 4;
-      if (j < cnt) {
-        if (a0 + j + 3 < nnz) cb[u] = __builtin_nontemporal_load((const i4*)(colidx + a0 + j));
-        else
-          for (int t = 0; t < 4; ++t) cb[u][t] = a0 + j + t < nnz ? colidx[a0 + j + t] : 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < VC; ++u) {
-      const int j = (u * WAVE + lane) * VE;
-      if (j < cnt) {
-        if (a0 + j + VE - 1 < nnz) vb[u] = __builtin_nontemporal_load((const vv*)(val + a0 + j));
-        else
-          for (int t = 0; t < VE; ++t) vb[u][t] = a0 + j + t < nnz ? val[a0 + j + t] : (T)0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CC; ++u) {
-      const int j = (u * WAVE + lane) * 4;
-      if (j < cnt) *(i4*)(scol + j) = cb[u];
-    }
-#pragma unroll
-    for (int u = 0; u < VC; ++u) {
-      const int j = (u * WAVE + lane) * VE;
-      if (j < cnt) *(vv*)(sval + j) = vb[u];
-    }
-    __builtin_amdgcn_wave_barrier();
-    T sm = (T)0;
-    if (i < P.n1d) {
-      // clamped into the staged window: a malformed rowptr reads wrong values, never outside it
-      const int32_t rb = min(max(rb_raw, nb), ne);
-      const int32_t re = min(max(re_raw, rb), ne);
-      const int32_t b = rb - a0, e = re - a0;
-      for (int32_t k = b; k < e; k += 8) {
-        int32_t c[8];
-        T av[8], xv[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int32_t kk = k + t < e ? k + t : b;
-          c[t] = scol[kk];
-          av[t] = sval[kk];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) xv[t] = x[(uint32_t)c[t] < nx ? c[t] : 0];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (k + t < e) {
-            const T tv = av[t] * xv[t];
-            sm = (k + t == b) ? tv : sm + tv;
-          }
-      }
-    }
-    // every lane's reads of this group are done before the next group is staged
-    __builtin_amdgcn_wave_barrier();
-    y[m] = sm;
+    y[m] = csr_group<T>(rowptr, colidx, val, x, g0, P.n1d, nnz, nx, scol, sval);
   }
   rows_to_owners<T, V>(y, out);
 }
