@@ -9,7 +9,7 @@ group executed as one kernel.  Inputs are resident in HBM before timing.
 Printed: one JSON line with the headline (fused algorithmic HBM GB/s), the
 roofline of the dominant kernel, the CPU oracle timed on a bounded sample,
 and the other legs of the metric (unfused GB/s, FP32, Jacobi stencil, CG
-iterations/s, and the continuous-batching server: its closed-loop saturation
+and BiCGSTAB iterations/s, and the continuous-batching server: its closed-loop saturation
 solves/s, then p50/p99 latency with Poisson arrivals at 0.5, 0.8 and 0.95 of
 saturation, the 0.8 point over the whole 4096-request stream) under "legs".
 Progress goes to stderr.
@@ -149,18 +149,25 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
     return out
 
 
-def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph):
+def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg"):
+    """CG on the Poisson matrix, or BiCGSTAB (solver="bicgstab") on the
+    nonsymmetric convection-diffusion matrix of the same shape."""
     c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
-    rowptr, col, val = synth.poisson_csr(m, dim)
+    if solver == "cg":
+        rowptr, col, val = synth.poisson_csr(m, dim)
+        seed = synth.CG64_SEED if dim == 2 else synth.CG256_SEED
+    else:
+        rowptr, col, val = synth.convdiff_csr(m, dim)
+        seed = synth.BICG256_SEED
     n = m ** dim
-    b = synth.rhs(n, synth.CG64_SEED if dim == 2 else synth.CG256_SEED)
+    b = synth.rhs(n, seed)
     hs = []
     for a, dt in ((rowptr, "i32"), (col, "i32"), (val, "f64"), (b, "f64")):
         s = c.store_create(list(a.shape), dt)
         c.store_write(s, a)
         hs.append(s)
     del rowptr, col, val
-    cg = dfx.apps.CG(c, *hs, n)
+    cg = (dfx.apps.CG if solver == "cg" else dfx.apps.BiCGSTAB)(c, *hs, n)
     for _ in range(8 if TUNE else 2):
         cg.iteration()
     c.sync()
@@ -319,7 +326,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="enable the library's launch-shape tuner (warm-ups extended to 8 executions)")
     ap.add_argument("--legs", default="all",
-                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,serve")
+                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,bicgstab256,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="fixed Poisson arrival rate; default: a saturation run, then 0.5/0.8/0.95 of it")
@@ -353,9 +360,9 @@ def main():
         print(json.dumps(out))
         return
     # legs: "all" (the default line), "headline", or a comma-separated list of
-    # bs_f64, bs_f32, jacobi, cg64, cg256, serve
+    # bs_f64, bs_f32, jacobi, cg64, cg256, bicgstab256, serve
     if args.legs == "all":
-        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "serve"}
+        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "bicgstab256", "serve"}
     elif args.legs == "headline":
         sel = set()
     else:
@@ -389,6 +396,12 @@ def main():
         log("cg 256^3")
         legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
+    if "bicgstab256" in sel:
+        log("bicgstab 256^3")
+        legs["bicgstab256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 20, True, True, "bicgstab")
+        legs["bicgstab256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 6, False, False, "bicgstab")
+        legs["bicgstab256_fused_graph"]["speedup_vs_unfused"] = (legs["bicgstab256_unfused"]["ms_per_iter"] /
+                                                                 legs["bicgstab256_fused_graph"]["ms_per_iter"])
     if "serve" in sel:
         log("serving: %d CG solves, %s" % (args.serve_requests, "load sweep" if args.serve_rate is None
                                               else "Poisson arrivals at %.0f/s" % args.serve_rate))

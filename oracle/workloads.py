@@ -21,6 +21,11 @@ host C library (oracle/cnum.c); reductions are exactly rounded.
                  sparse Krylov benchmark of section 7: q = A p, alpha = rho/(p.q),
                  x += alpha p, r -= alpha q, rho' = r.r, beta = rho'/rho,
                  p = beta p + r
+  bicgstab       BiCGSTAB (van der Vorst, SIAM J. Sci. Stat. Comput. 13(2),
+                 1992), unpreconditioned, the further Krylov method the
+                 evaluation's task-count table lists; the paper gives no
+                 formula, so the published recurrence is used with x0 = 0
+                 and the shadow residual r^ = r0 = b
 """
 from __future__ import annotations
 
@@ -163,4 +168,37 @@ def cg(rowptr, col, val, b, iters, tol=None):
         p = beta * p
         p = p + r
         hist.append(rho)
+    return x, hist
+
+
+def bicgstab(rowptr, col, val, b, iters):
+    """BiCGSTAB from x0 = 0, shadow residual r^ = r0 = b, started from
+    rho = alpha = omega = 1 and p = v = 0 (so the first p is r0).  One
+    iteration, in this order:
+      rho' = r^.r;  beta = (rho'/rho) (alpha/omega);  rho = rho'
+      p = r + beta (p - omega v);  v = A p;  alpha = rho / (r^.v)
+      s = r - alpha v;  t = A s;  omega = (t.s) / (t.t)
+      x = (x + alpha p) + omega s;  r = s - omega t
+    Returns (x, history) where history[k] = r_k . r_k (k = 0..iters)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    rhat = b.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho = alpha = omega = 1.0
+    hist = [cnum.fsum_prod(r, r)]
+    for _ in range(iters):
+        rho_new = cnum.fsum_prod(rhat, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        rho = rho_new
+        p = r + beta * (p - omega * v)
+        v = cnum.spmv(rowptr, col, val, p)
+        alpha = rho / cnum.fsum_prod(rhat, v)
+        s = r - alpha * v
+        t = cnum.spmv(rowptr, col, val, s)
+        omega = cnum.fsum_prod(t, s) / cnum.fsum_prod(t, t)
+        x = (x + alpha * p) + omega * s
+        r = s - omega * t
+        hist.append(cnum.fsum_prod(r, r))
     return x, hist

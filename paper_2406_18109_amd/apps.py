@@ -1,4 +1,4 @@
-"""Task streams of the three workloads of section 7, issued through the binding.
+"""Task streams of the workloads of section 7 (and BiCGSTAB), issued through the binding.
 
 These play the part of the application (the NumPy/SciPy-style program whose
 library calls become index tasks): each function submits tasks and drops its
@@ -148,3 +148,75 @@ class CG:
         c.submit("copy", [], [(self.rho_new, N, "R"), (self.rho, N, "W")])
         c.submit("mul", d, [(p, T, "R"), (self.beta, N, "R"), (p, T, "W")])
         c.submit("add", d, [(p, T, "R"), (r, T, "R"), (p, T, "W")])
+
+
+class BiCGSTAB:
+    """BiCGSTAB (van der Vorst 1992), unpreconditioned, as a SciPy-style
+    program would issue it: two SpMVs, four dot products (r^.r, r^.v, t.s,
+    t.t) and the residual norm r.r per iteration, scalar divides, axpys.
+    x0 = 0, shadow residual r^ = r0 = b; rho, alpha and omega start at 1 and
+    p, v at 0, so the first direction is r0.  One iteration:
+      rho' = r^.r; beta = (rho'/rho)(alpha/omega); rho = rho'
+      p = r + beta (p - omega v); v = A p; alpha = rho / (r^.v)
+      s = r - alpha v; t = A s; omega = (t.s)/(t.t)
+      x = (x + alpha p) + omega s; r = s - omega t; rr = r.r
+    The first rho' is formed at set-up, each later one at the end of the
+    previous iteration."""
+
+    def __init__(self, ctx: Context, rowptr, col, val, b, n, points=1):
+        self.ctx, self.n = ctx, n
+        c = ctx
+        self.rowptr, self.col, self.val = rowptr, col, val
+        self.none = c.part_none()
+        self.tile = c.part_tiling([n // points])
+        self.img = c.part_image(col, self.none)
+        self.d = [points]
+        vec = lambda: c.store_create([n], "f64")
+        sc = lambda: c.store_create([], "f64")
+        self.x, self.r, self.rhat, self.p, self.v, self.s, self.t = (vec() for _ in range(7))
+        self.rho, self.rho_new, self.alpha, self.omega = sc(), sc(), sc(), sc()
+        self.beta, self.rv, self.ts, self.tt, self.rr = sc(), sc(), sc(), sc(), sc()
+        T, N, d = self.tile, self.none, self.d
+        c.submit("fill", d, [(self.x, T, "W")], (0.0,))
+        c.submit("copy", d, [(b, T, "R"), (self.r, T, "W")])
+        c.submit("copy", d, [(b, T, "R"), (self.rhat, T, "W")])
+        c.submit("fill", d, [(self.p, T, "W")], (0.0,))
+        c.submit("fill", d, [(self.v, T, "W")], (0.0,))
+        for sc_ in (self.rho, self.alpha, self.omega):
+            c.submit("fill", [], [(sc_, N, "W")], (1.0,))
+        c.submit("dot", d, [(self.r, T, "R"), (self.r, T, "R"), (self.rr, N, "Rd")], (1,))
+        c.submit("dot", d, [(self.rhat, T, "R"), (self.r, T, "R"), (self.rho_new, N, "Rd")], (1,))
+
+    def iteration(self):
+        c, T, N, d = self.ctx, self.tile, self.none, self.d
+        x, r, rhat, p, v, s, t = self.x, self.r, self.rhat, self.p, self.v, self.s, self.t
+        sp = lambda src, dst: c.submit("spmv_csr", d, [(self.rowptr, N, "R"), (self.col, N, "R"),
+                                                        (self.val, N, "R"), (src, self.img, "R"), (dst, T, "W")])
+        # beta = (rho'/rho) * (alpha/omega): two temporaries the expression drops
+        q1, q2 = c.store_create([], "f64"), c.store_create([], "f64")
+        c.submit("div", [], [(self.rho_new, N, "R"), (self.rho, N, "R"), (q1, N, "W")])
+        c.submit("div", [], [(self.alpha, N, "R"), (self.omega, N, "R"), (q2, N, "W")])
+        c.submit("mul", [], [(q1, N, "R"), (q2, N, "R"), (self.beta, N, "W")])
+        c.store_release(q1)
+        c.store_release(q2)
+        c.submit("copy", [], [(self.rho_new, N, "R"), (self.rho, N, "W")])
+        c.submit("axpy", d, [(self.omega, N, "R"), (v, T, "R"), (p, T, "RW")], (-1.0,))
+        c.submit("mul", d, [(p, T, "R"), (self.beta, N, "R"), (p, T, "W")])
+        c.submit("add", d, [(p, T, "R"), (r, T, "R"), (p, T, "W")])
+        sp(p, v)
+        c.submit("dot", d, [(rhat, T, "R"), (v, T, "R"), (self.rv, N, "Rd")], (1,))
+        c.submit("div", [], [(self.rho, N, "R"), (self.rv, N, "R"), (self.alpha, N, "W")])
+        c.submit("copy", d, [(r, T, "R"), (s, T, "W")])
+        c.submit("axpy", d, [(self.alpha, N, "R"), (v, T, "R"), (s, T, "RW")], (-1.0,))
+        sp(s, t)
+        c.submit("dot", d, [(t, T, "R"), (s, T, "R"), (self.ts, N, "Rd")], (1,))
+        c.submit("dot", d, [(t, T, "R"), (t, T, "R"), (self.tt, N, "Rd")], (1,))
+        c.submit("div", [], [(self.ts, N, "R"), (self.tt, N, "R"), (self.omega, N, "W")])
+        c.submit("axpy", d, [(self.alpha, N, "R"), (p, T, "R"), (x, T, "RW")], (1.0,))
+        c.submit("axpy", d, [(self.omega, N, "R"), (s, T, "R"), (x, T, "RW")], (1.0,))
+        c.submit("copy", d, [(s, T, "R"), (r, T, "W")])
+        c.submit("axpy", d, [(self.omega, N, "R"), (t, T, "R"), (r, T, "RW")], (-1.0,))
+        c.submit("dot", d, [(r, T, "R"), (r, T, "R"), (self.rr, N, "Rd")], (1,))
+        # the next iteration's rho' = r^.r, issued here so that it joins this
+        # window (also when one iteration is captured as a graph)
+        c.submit("dot", d, [(rhat, T, "R"), (r, T, "R"), (self.rho_new, N, "Rd")], (1,))

@@ -139,6 +139,19 @@ def poisson_csr(m: int, dim: int):
     return rowptr.astype(np.int32), col, val
 
 
+
+def convdiff_csr(m: int, dim: int, c: float = 0.5):
+    """A nonsymmetric variant of poisson_csr: first-order upwind convection
+    along x, so the diagonal is 2*dim + c and the west neighbour -1 - c (c
+    exactly representable keeps every value exact).  Weakly diagonally
+    dominant and irreducible, hence nonsingular.  Same CSR layout."""
+    rowptr, col, val = poisson_csr(m, dim)
+    rows = np.repeat(np.arange(rowptr.size - 1, dtype=np.int64), np.diff(rowptr))
+    val = val.copy()
+    val[col == rows] += c
+    val[col == rows - 1] -= c   # x fastest: column i-1 is the west neighbour when it exists
+    return rowptr, col, val
+
 def rhs(n: int, seed: int, stream: int = 0) -> np.ndarray:
     """Right-hand side uniform in [-1, 1)."""
     return uniform(seed, stream, n, -1.0, 1.0)
@@ -146,6 +159,7 @@ def rhs(n: int, seed: int, stream: int = 0) -> np.ndarray:
 
 CG64_SEED = 2001
 CG256_SEED = 2002
+BICG256_SEED = 2003   # BiCGSTAB on the 256^3 convection-diffusion system
 
 
 # --------------------------------------------------------------------------

@@ -196,6 +196,31 @@ def test_cg_windows():
     assert kinds == [[1], [2], [0], [2], [0]]
 
 
+def test_bicgstab_windows():
+    ctx = dfx.Context(device=-1, window_size=16)
+    n = 64
+    rp = ctx.store_create([n + 1], "i32")
+    col = ctx.store_create([5 * n], "i32")
+    val = ctx.store_create([5 * n], "f64")
+    b = ctx.store_create([n], "f64")
+    bi = dfx.apps.BiCGSTAB(ctx, rp, col, val, b, n)
+    ctx.flush()
+    g0 = len(ctx.groups())
+    for _ in range(4):
+        bi.iteration()
+    ctx.flush()
+    g = ctx.groups()[g0:]
+    lens = [x["prefix_len"] for x in g]
+    # 22 tasks per iteration in 8 groups:
+    # [beta's two divides and product, rho <- rho'] [p - omega v, * beta, + r]
+    # [spmv, r^.v] [alpha] [s = r - alpha v (copy, axpy)] [spmv, t.s, t.t] [omega]
+    # [x += alpha p, x += omega s, r = s - omega t (copy, axpy), r.r, next rho' = r^.r]
+    assert lens == [4, 3, 2, 1, 2, 3, 1, 6] * 4
+    assert [x["pass_kind"] for x in g[:8]] == [[2], [0], [1], [2], [0], [1], [2], [0]]
+    # beta's two quotients are temporaries of the scalar window
+    assert len(g[0]["temporaries"]) == 2
+
+
 def test_validation_rejects_illegal_tasks_and_keeps_window():
     ctx = dfx.Context(device=-1, window_size=64)
     a = ctx.store_create([8], "f64")
