@@ -113,7 +113,13 @@ typedef struct {
                             candidate must beat the default by 3 %).  Results do not depend on
                             the choice: every candidate keeps each block's tiles an aligned
                             subtree of the reduction tree. */
-  int32_t reserved[8];
+  int32_t auto_window;   /* 0: the window holds window_size tasks.  > 0: automatic window
+                            sizing (the evaluation's choice of window sizes): when a full
+                            window fuses as a whole, it is not dispatched; its size doubles,
+                            up to auto_window (>= window_size, else EINVAL), and the tasks
+                            stay buffered.  Once a full window does not fuse as a whole, the
+                            size stays.  Flushes are not affected.  Needs fuse = 1. */
+  int32_t reserved[7];
 } dfx_config;
 
 typedef struct {
@@ -221,6 +227,8 @@ int dfx_graph_destroy(dfx_ctx* ctx, int32_t graph_id);
 /* ---- introspection ---------------------------------------------------- */
 int dfx_stats_get(dfx_ctx* ctx, dfx_stats* out);
 int dfx_stats_reset(dfx_ctx* ctx);
+/* Current window size: window_size, or what automatic sizing has grown it to. */
+int dfx_window_size(dfx_ctx* ctx, int32_t* out);
 /* Number of groups recorded since the last reset, and the i-th one. */
 int dfx_group_count(dfx_ctx* ctx, int64_t* n);
 int dfx_group_get(dfx_ctx* ctx, int64_t i, dfx_group_info* out);

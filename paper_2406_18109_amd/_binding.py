@@ -40,7 +40,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 class dfx_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
                 ("dealloc", FREE_FN), ("alloc_user", C.c_void_p), ("window_size", C.c_int32),
-                ("fuse", C.c_int32), ("memo", C.c_int32), ("tune", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("fuse", C.c_int32), ("memo", C.c_int32), ("tune", C.c_int32), ("auto_window", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class dfx_arg(C.Structure):
@@ -119,6 +120,7 @@ SIGNATURES = {
     "dfx_graph_destroy": (C.c_int, [C.c_void_p, C.c_int32]),
     "dfx_stats_get": (C.c_int, [C.c_void_p, C.POINTER(dfx_stats)]),
     "dfx_stats_reset": (C.c_int, [C.c_void_p]),
+    "dfx_window_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "dfx_group_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "dfx_group_get": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(dfx_group_info)]),
     "dfx_serve_start": (C.c_int, [C.c_void_p, C.POINTER(dfx_serve_cfg)]),
@@ -195,7 +197,7 @@ class Context:
     """One dfx context (dfx_create ... dfx_destroy)."""
 
     def __init__(self, device: int = 0, window_size: int = 16, fuse: bool = True, memo: bool = True,
-                 stream=None, allocator: str = "torch", tune: bool = False):
+                 stream=None, allocator: str = "torch", tune: bool = False, auto_window: int = 0):
         self.L = lib()
         cfg = dfx_config()
         cfg.device = device
@@ -203,6 +205,7 @@ class Context:
         cfg.fuse = 1 if fuse else 0
         cfg.memo = 1 if memo else 0
         cfg.tune = 1 if tune else 0
+        cfg.auto_window = auto_window
         self._alloc = None
         self.torch_stream = None
         if device >= 0:
@@ -405,6 +408,11 @@ class Context:
     def serve_stop(self):
         self._chk(self.L.dfx_serve_stop(self.h))
         self._serve_keep = {}
+
+    def window_size(self) -> int:
+        n = C.c_int32()
+        self._chk(self.L.dfx_window_size(self.h, C.byref(n)))
+        return n.value
 
     def groups(self) -> list:
         n = C.c_int64()

@@ -1260,7 +1260,10 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-static int dispatch_one(Ctx& c) {
+// may_grow: called because the window filled up (not from a flush); under
+// auto_window a full window whose every task fuses is kept and the window
+// size doubled instead
+static int dispatch_one(Ctx& c, bool may_grow = false) {
   if (c.window.empty()) return DFX_OK;
   std::vector<int64_t> order;
   std::string key = canonical_key(c, order);
@@ -1298,6 +1301,12 @@ static int dispatch_one(Ctx& c) {
     }
   } else {
     c.stats.memo_hits += 1;
+  }
+  if (may_grow && c.cfg.auto_window > 0 && c.window_cur < c.cfg.auto_window &&
+      plan->prefix == (int)c.window.size()) {
+    c.window_cur = (int)std::min<int64_t>(2 * (int64_t)c.window_cur, c.cfg.auto_window);
+    if (owned && !c.analysis_only && !c.capturing) release_plan(c, *owned);
+    return DFX_OK;
   }
   for (auto& p : plan->passes) {
     int rc = run_pass(c, p, order);
@@ -1365,8 +1374,11 @@ const char* dfx_last_error(dfx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null
 int dfx_create(const dfx_config* cfg, dfx_ctx** out) {
   if (!cfg || !out) return DFX_EINVAL;
   if (cfg->window_size < 1) return DFX_EINVAL;
+  if (cfg->auto_window < 0 || (cfg->auto_window > 0 && (cfg->auto_window < cfg->window_size || !cfg->fuse)))
+    return DFX_EINVAL;
   dfx_ctx* c = new dfx_ctx();
   c->cfg = *cfg;
+  c->window_cur = cfg->window_size;
   c->stream = (hipStream_t)cfg->stream;
   c->analysis_only = cfg->device < 0;
   if (!c->analysis_only) {
@@ -1577,11 +1589,17 @@ int dfx_submit(dfx_ctx* c, const dfx_task* task) {
     if (seen.insert(a.store).second) c->stores.at(a.store).pending += 1;
   c->window.push_back(std::move(t));
   c->stats.tasks_submitted += 1;
-  if ((int)c->window.size() >= c->cfg.window_size) return dispatch_one(*c);
+  if ((int)c->window.size() >= c->window_cur) return dispatch_one(*c, true);
   return DFX_OK;
 }
 
 int dfx_flush(dfx_ctx* c) { return c ? flush(*c) : DFX_EINVAL; }
+
+int dfx_window_size(dfx_ctx* c, int32_t* out) {
+  if (!c || !out) return DFX_EINVAL;
+  *out = c->window_cur;
+  return DFX_OK;
+}
 
 int dfx_sync(dfx_ctx* c) {
   if (!c) return DFX_EINVAL;

@@ -147,6 +147,7 @@ struct Ctx {
   std::unordered_map<std::string, int> part_index;
 
   std::deque<TaskRec> window;
+  int window_cur = 1;       // tasks that fill the window (grows under auto_window)
   int64_t next_seq = 0;
 
   std::unordered_map<std::string, std::unique_ptr<Plan>> memo;

@@ -221,6 +221,66 @@ def test_bicgstab_windows():
     assert len(g[0]["temporaries"]) == 2
 
 
+def _bs_groups(window, auto):
+    ctx = dfx.Context(device=-1, window_size=window, auto_window=auto)
+    n = 1 << 10
+    S, K, T = (ctx.store_create([n], "f64") for _ in range(3))
+    r, sig, rv = (ctx.store_create([], "f64") for _ in range(3))
+    dfx.apps.black_scholes(ctx, S, K, T, r, sig, rv, n, "f64", 1)
+    ctx.flush()
+    return [g["prefix_len"] for g in ctx.groups()], ctx.window_size()
+
+
+def _solver_groups(cls, window, auto, iters=6):
+    ctx = dfx.Context(device=-1, window_size=window, auto_window=auto)
+    n = 64
+    rp = ctx.store_create([n + 1], "i32")
+    col = ctx.store_create([5 * n], "i32")
+    val = ctx.store_create([5 * n], "f64")
+    b = ctx.store_create([n], "f64")
+    s = cls(ctx, rp, col, val, b, n)
+    for _ in range(iters):
+        s.iteration()
+    ctx.flush()
+    return [g["prefix_len"] for g in ctx.groups()], ctx.window_size()
+
+
+def test_auto_window_grows_while_everything_fuses():
+    """Automatic window sizing (the evaluation's choice of window sizes): a
+    full window that fuses as a whole doubles instead of being dispatched."""
+    lens, w = _bs_groups(2, 0)
+    assert lens == [2] * 14 and w == 2
+    lens, w = _bs_groups(2, 64)
+    assert lens == [28] and w == 32          # 2 -> 4 -> 8 -> 16 -> 32, then the flush
+    lens, w = _bs_groups(2, 16)
+    assert lens == [16, 12] and w == 16      # capped
+    for cls in (dfx.apps.CG, dfx.apps.BiCGSTAB):
+        fixed, _ = _solver_groups(cls, 16, 0)
+        auto, w = _solver_groups(cls, 1, 64)
+        assert auto == fixed and w == 8, cls.__name__
+
+
+def test_auto_window_jacobi_matches_fixed():
+    def run(window, auto):
+        ctx = dfx.Context(device=-1, window_size=window, auto_window=auto)
+        G = ctx.store_create([34, 34], "f64")
+        J = dfx.apps.Jacobi(ctx, G, 34)
+        for _ in range(5):
+            J.sweep()
+        ctx.flush()
+        return [g["prefix_len"] for g in ctx.groups()], ctx.window_size()
+    fixed, _ = run(16, 0)
+    auto, w = run(1, 256)
+    assert auto == fixed and w <= 16
+
+
+def test_auto_window_config_checked():
+    for kw in (dict(window_size=8, auto_window=4), dict(window_size=1, auto_window=-1),
+               dict(window_size=1, auto_window=8, fuse=False)):
+        with pytest.raises(dfx.DfxError):
+            dfx.Context(device=-1, **kw)
+
+
 def test_validation_rejects_illegal_tasks_and_keeps_window():
     ctx = dfx.Context(device=-1, window_size=64)
     a = ctx.store_create([8], "f64")

@@ -1,0 +1,43 @@
+"""Automatic window sizing on the GPU: the windows it settles on give the
+same groups, hence the same bits, as a fixed window large enough for every
+fusion (Black-Scholes from a window of 2, CG from 1)."""
+import numpy as np
+import pytest
+
+import paper_2406_18109_amd as dfx
+import synth
+from gpu_util import bs_run, note, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_auto_window_black_scholes_bit_identical():
+    n = 3 * 4096 + 77
+    note("auto window: black-scholes n=%d" % n)
+    c = dfx.Context(device=0, window_size=2, auto_window=64)
+    _, call_a, put_a = bs_run(c, n, passes=2)
+    assert [g["prefix_len"] for g in c.groups()] == [28, 28] and c.window_size() == 32
+    c.close()
+    c = dfx.Context(device=0, window_size=64)
+    _, call_f, put_f = bs_run(c, n, passes=2)
+    c.close()
+    assert np.array_equal(call_a, call_f) and np.array_equal(put_a, put_f)
+
+
+def test_auto_window_cg_bit_identical():
+    m = 96
+    note("auto window: cg %d^2" % m)
+    rowptr, col, val = synth.poisson_csr(m, 2)
+    b = synth.rhs(m * m, synth.CG64_SEED)
+    out = []
+    for window, auto in ((1, 64), (16, 0)):
+        c = dfx.Context(device=0, window_size=window, auto_window=auto)
+        cg = dfx.apps.CG(c, *[upload(c, a) for a in (rowptr, col, val, b)], m * m)
+        rho = []
+        for _ in range(20):
+            cg.iteration()
+            rho.append(float(c.store_read(cg.rho, [], "f64")))
+        out.append((rho, c.store_read(cg.x, [m * m], "f64"), [g["prefix_len"] for g in c.groups()]))
+        c.close()
+    (ra, xa, ga), (rf, xf, gf) = out
+    assert ga == gf and ra == rf and np.array_equal(xa, xf)
