@@ -1274,9 +1274,17 @@ static int dispatch_one(Ctx& c, bool may_grow = false) {
     auto it = c.memo.find(key);
     if (it != c.memo.end()) { plan = it->second.get(); hit = true; }
   }
+  const bool grow = may_grow && c.cfg.auto_window > 0 && c.window_cur < c.cfg.auto_window;
   if (!plan) {
     const double t0 = now_s();
     const int f = c.cfg.fuse ? longest_prefix(c) : 1;
+    // the decision needs the analysis only: no plan is built for a window
+    // that keeps growing (its stores may still be named by the application)
+    if (grow && f == (int)c.window.size()) {
+      c.stats.analysis_seconds += now_s() - t0;
+      c.window_cur = (int)std::min<int64_t>(2 * (int64_t)c.window_cur, c.cfg.auto_window);
+      return DFX_OK;
+    }
     std::set<int64_t> temps;
     if (c.cfg.fuse) temps = temporaries(c, f);
     owned.reset(new Plan());
@@ -1302,10 +1310,8 @@ static int dispatch_one(Ctx& c, bool may_grow = false) {
   } else {
     c.stats.memo_hits += 1;
   }
-  if (may_grow && c.cfg.auto_window > 0 && c.window_cur < c.cfg.auto_window &&
-      plan->prefix == (int)c.window.size()) {
+  if (grow && hit && plan->prefix == (int)c.window.size()) {
     c.window_cur = (int)std::min<int64_t>(2 * (int64_t)c.window_cur, c.cfg.auto_window);
-    if (owned && !c.analysis_only && !c.capturing) release_plan(c, *owned);
     return DFX_OK;
   }
   for (auto& p : plan->passes) {
