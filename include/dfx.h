@@ -227,6 +227,20 @@ int dfx_graph_destroy(dfx_ctx* ctx, int32_t graph_id);
 /* ---- introspection ---------------------------------------------------- */
 int dfx_stats_get(dfx_ctx* ctx, dfx_stats* out);
 int dfx_stats_reset(dfx_ctx* ctx);
+/* On-disk plan cache (the paper's stated future work: reuse analysis and
+ * lowering across runs).  save writes every memoised plan with its
+ * canonical key (partitions encoded by structure, stores by first
+ * appearance, so a key means the same in every context); load adds the
+ * file's plans to the memo table (keys already present are kept) and
+ * reports how many it added.  The file is bound to the library build that
+ * wrote it: another build's file, a wrong magic, a checksum mismatch or a
+ * truncated body is rejected with DFX_EINVAL and nothing is added; a
+ * missing file gives DFX_ENOTFOUND.  load needs memo = 1 and fuse = 1
+ * (DFX_ESTATE).  A pass saved while its launch shape was being tuned is
+ * stored with the default shape.  The file is trusted input: it is meant to
+ * be one that dfx_plan_cache_save wrote. */
+int dfx_plan_cache_save(dfx_ctx* ctx, const char* path, int64_t* n_saved);
+int dfx_plan_cache_load(dfx_ctx* ctx, const char* path, int64_t* n_loaded);
 /* Current window size: window_size, or what automatic sizing has grown it to. */
 int dfx_window_size(dfx_ctx* ctx, int32_t* out);
 /* Number of groups recorded since the last reset, and the i-th one. */

@@ -121,6 +121,8 @@ SIGNATURES = {
     "dfx_stats_get": (C.c_int, [C.c_void_p, C.POINTER(dfx_stats)]),
     "dfx_stats_reset": (C.c_int, [C.c_void_p]),
     "dfx_window_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "dfx_plan_cache_save": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
+    "dfx_plan_cache_load": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "dfx_group_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "dfx_group_get": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(dfx_group_info)]),
     "dfx_serve_start": (C.c_int, [C.c_void_p, C.POINTER(dfx_serve_cfg)]),
@@ -408,6 +410,16 @@ class Context:
     def serve_stop(self):
         self._chk(self.L.dfx_serve_stop(self.h))
         self._serve_keep = {}
+
+    def plan_cache_save(self, path) -> int:
+        n = C.c_int64()
+        self._chk(self.L.dfx_plan_cache_save(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
+
+    def plan_cache_load(self, path) -> int:
+        n = C.c_int64()
+        self._chk(self.L.dfx_plan_cache_load(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
 
     def window_size(self) -> int:
         n = C.c_int32()

@@ -497,6 +497,25 @@ static std::set<int64_t> temporaries(Ctx& c, int f) {
 // privileges, and each store's rank, shape, dtype and live bit.
 static void put(std::string& k, const void* p, size_t n) { k.append((const char*)p, n); }
 
+// A partition by its structure (kind, tiles, offsets, projection), so that a
+// key means the same in every context; interned handles make this
+// equivalent to handle equality inside one context.
+static void put_part(std::string& k, const Ctx& c, int part) {
+  const PartRec& p = c.parts[part];
+  put(k, &p.kind, 4);
+  put(k, &p.ndim, 4);
+  put(k, p.tile, 8 * p.ndim);
+  put(k, p.off, 8 * p.ndim);
+  int32_t np = p.proj >= 0 ? 1 : 0;
+  put(k, &np, 4);
+  if (np) {
+    const ProjRec& r = c.projs[p.proj];
+    put(k, &r.nin, 4);
+    put(k, &r.nout, 4);
+    put(k, r.keep, 4 * r.nout);
+  }
+}
+
 static std::string canonical_key(Ctx& c, std::vector<int64_t>& order) {
   std::unordered_map<int64_t, int> idx;
   order.clear();
@@ -527,9 +546,9 @@ static std::string canonical_key(Ctx& c, std::vector<int64_t>& order) {
       if (p.kind == PK_IMAGE) {
         int32_t tag = -2 - cid(p.img_src);
         put(k, &tag, 4);
-        put(k, &p.img_part, 4);
+        put_part(k, c, p.img_part);
       } else {
-        put(k, &a.part, 4);
+        put_part(k, c, a.part);
       }
       put(k, &a.priv, 4);
     }
@@ -1369,6 +1388,67 @@ static int flush(Ctx& c) {
 // C ABI
 using namespace dfx;
 
+namespace {
+constexpr char kPlanMagic[8] = {'D', 'F', 'X', 'P', 'L', 'A', 'N', '1'};
+const std::string& build_stamp() {
+  static const std::string s = std::string(dfx_version()) + " " + __DATE__ + " " + __TIME__;
+  return s;
+}
+uint64_t fnv1a(const char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) { h ^= (unsigned char)p[i]; h *= 1099511628211ull; }
+  return h;
+}
+struct Wr {
+  std::string b;
+  template <class T> void v(const T& x) { b.append((const char*)&x, sizeof(T)); }
+  template <class T> void vec(const std::vector<T>& x) {
+    const uint32_t n = (uint32_t)x.size();
+    v(n);
+    if (n) b.append((const char*)x.data(), n * sizeof(T));
+  }
+  void str(const std::string& x) {
+    const uint32_t n = (uint32_t)x.size();
+    v(n);
+    b.append(x);
+  }
+};
+struct Rd {
+  const char* p;
+  const char* e;
+  bool ok = true;
+  template <class T> void v(T& x) {
+    if (!ok || (size_t)(e - p) < sizeof(T)) { ok = false; x = T(); return; }
+    std::memcpy(&x, p, sizeof(T));
+    p += sizeof(T);
+  }
+  template <class T> void vec(std::vector<T>& x) {
+    uint32_t n = 0;
+    v(n);
+    if (!ok || n > (1u << 24) || (size_t)(e - p) < (size_t)n * sizeof(T)) { ok = false; return; }
+    x.resize(n);
+    if (n) std::memcpy(x.data(), p, n * sizeof(T));
+    p += (size_t)n * sizeof(T);
+  }
+  void str(std::string& x) {
+    uint32_t n = 0;
+    v(n);
+    if (!ok || (size_t)(e - p) < n) { ok = false; return; }
+    x.assign(p, n);
+    p += n;
+  }
+};
+template <class IO, class P> void pass_fields(IO& io, P& q) {
+  io.v(q.kind); io.v(q.dtype); io.v(q.is1d); io.v(q.rows); io.v(q.cols); io.v(q.n1d);
+  io.v(q.n_tiles); io.v(q.strips); io.v(q.tiles_per_wave); io.v(q.grid); io.v(q.nreg);
+  io.v(q.tier); io.v(q.unit_cols);
+  io.vec(q.ins); io.vec(q.outs); io.vec(q.out_reg); io.vec(q.bc_cstore); io.vec(q.bc_reg);
+  io.vec(q.red_cstore); io.vec(q.red_init);
+  io.v(q.spmv_rowptr); io.v(q.spmv_col); io.v(q.spmv_val); io.v(q.spmv_x);
+  io.vec(q.code); io.vec(q.imm); io.v(q.alg_bytes); io.vec(q.tune_cand);
+}
+}  // namespace
+
 struct dfx_ctx : public dfx::Ctx {};
 
 extern "C" {
@@ -1600,6 +1680,96 @@ int dfx_submit(dfx_ctx* c, const dfx_task* task) {
 }
 
 int dfx_flush(dfx_ctx* c) { return c ? flush(*c) : DFX_EINVAL; }
+
+// ---- on-disk plan cache ----------------------------------------------------
+// File: magic, format version, build stamp, FNV-1a 64 checksum of the body,
+// then the body: entry count and, per entry, the canonical key and the plan.
+// Plans name stores by canonical index and carry no device state (workspaces
+// are allocated at first execution), so a plan is valid for its key in any
+// context of the same build.
+
+
+int dfx_plan_cache_save(dfx_ctx* c, const char* path, int64_t* n_saved) {
+  if (!c || !path) return DFX_EINVAL;
+  Wr body;
+  body.v((uint32_t)c->memo.size());
+  for (const auto& kv : c->memo) {
+    const Plan& pl = *kv.second;
+    body.str(kv.first);
+    body.v(pl.prefix);
+    body.vec(pl.temps);
+    body.v(pl.alg_bytes);
+    body.v((uint32_t)pl.passes.size());
+    for (const PassPlan& p : pl.passes) {
+      PassPlan q = p;   // a pass still being tuned is saved with its default shape
+      if (!q.tune_cand.empty()) set_shape(q, q.tune_cand[0]);
+      pass_fields(body, q);
+    }
+  }
+  Wr head;
+  head.b.append(kPlanMagic, 8);
+  head.v((uint32_t)sizeof(PassPlan));
+  head.str(build_stamp());
+  head.v(fnv1a(body.b.data(), body.b.size()));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(*c, DFX_EINVAL, std::string("cannot write ") + path);
+  const bool ok = std::fwrite(head.b.data(), 1, head.b.size(), f) == head.b.size() &&
+                  std::fwrite(body.b.data(), 1, body.b.size(), f) == body.b.size();
+  if (std::fclose(f) != 0 || !ok) return fail(*c, DFX_EINVAL, std::string("write failed: ") + path);
+  if (n_saved) *n_saved = (int64_t)c->memo.size();
+  return DFX_OK;
+}
+
+int dfx_plan_cache_load(dfx_ctx* c, const char* path, int64_t* n_loaded) {
+  if (!c || !path) return DFX_EINVAL;
+  if (!c->cfg.memo || !c->cfg.fuse) return fail(*c, DFX_ESTATE, "the plan cache needs memo = 1 and fuse = 1");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(*c, DFX_ENOTFOUND, std::string("cannot read ") + path);
+  std::string data;
+  char buf[1 << 16];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) data.append(buf, got);
+  std::fclose(f);
+  Rd rd{data.data(), data.data() + data.size()};
+  if (data.size() < 8 || std::memcmp(data.data(), kPlanMagic, 8) != 0)
+    return fail(*c, DFX_EINVAL, "not a plan cache file");
+  rd.p += 8;
+  uint32_t pp_size = 0;
+  std::string stamp;
+  uint64_t sum = 0;
+  rd.v(pp_size);
+  rd.str(stamp);
+  rd.v(sum);
+  if (!rd.ok || pp_size != sizeof(PassPlan) || stamp != build_stamp())
+    return fail(*c, DFX_EINVAL, "plan cache written by another build of the library");
+  if (fnv1a(rd.p, (size_t)(rd.e - rd.p)) != sum) return fail(*c, DFX_EINVAL, "plan cache checksum mismatch");
+  uint32_t n = 0;
+  rd.v(n);
+  std::vector<std::pair<std::string, std::unique_ptr<Plan>>> got_plans;
+  for (uint32_t i = 0; i < n && rd.ok; ++i) {
+    std::string key;
+    auto pl = std::make_unique<Plan>();
+    uint32_t np = 0;
+    rd.str(key);
+    rd.v(pl->prefix);
+    rd.vec(pl->temps);
+    rd.v(pl->alg_bytes);
+    rd.v(np);
+    if (!rd.ok || np > 64) { rd.ok = false; break; }
+    pl->passes.resize(np);
+    for (PassPlan& q : pl->passes) {
+      pass_fields(rd, q);
+      if (!c->cfg.tune) q.tune_cand.clear();
+    }
+    got_plans.emplace_back(std::move(key), std::move(pl));
+  }
+  if (!rd.ok || rd.p != rd.e) return fail(*c, DFX_EINVAL, "malformed plan cache");
+  int64_t added = 0;
+  for (auto& kv : got_plans)
+    if (c->memo.size() < 4096 && c->memo.emplace(std::move(kv.first), std::move(kv.second)).second) ++added;
+  if (n_loaded) *n_loaded = added;
+  return DFX_OK;
+}
 
 int dfx_window_size(dfx_ctx* c, int32_t* out) {
   if (!c || !out) return DFX_EINVAL;
