@@ -29,12 +29,12 @@ def _run(c):
 def test_loaded_plans_bit_identical(tmp_path):
     path = str(tmp_path / "plans.bin")
     note("plan cache: save")
-    a = dfx.Context(device=0, window_size=16)
+    a = dfx.Context(device=0, window_size=64)
     ra = _run(a)
     n = a.plan_cache_save(path)
     a.close()
     note("plan cache: load %d plans" % n)
-    b = dfx.Context(device=0, window_size=16)
+    b = dfx.Context(device=0, window_size=64)
     assert b.plan_cache_load(path) == n
     rb = _run(b)
     st = b.stats()
