@@ -67,6 +67,13 @@ static int fail(Ctx& c, int code, const std::string& msg) {
   return code;
 }
 
+// A fused group that one kernel cannot hold (streams, ops, reduction slots,
+// live values): the dispatcher answers it with a shorter prefix.
+static int fail_limit(Ctx& c, const std::string& msg) {
+  c.over_limit = true;
+  return fail(c, DFX_EUNSUPPORTED, msg);
+}
+
 #define HIPCHK(c, expr)                                                             \
   do {                                                                              \
     hipError_t e__ = (expr);                                                        \
@@ -788,7 +795,7 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
       } break;
       case K_RED: {
         const int slot = (int)out.red_cstore.size();
-        if (slot >= VM_MAXRED) return fail(c, DFX_EUNSUPPORTED, "too many reductions in one pass");
+        if (slot >= VM_MAXRED) return fail_limit(c, "too many reductions in one pass");
         const int cs = L.cidx.at(A.back().store);
         out.red_cstore.push_back(cs);
         out.red_init.push_back(!t->imm.empty() && t->imm[0] != 0);
@@ -854,7 +861,7 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   if (out.ins.size() > (size_t)VM_MAXIN || out.bc_cstore.size() > (size_t)VM_MAXBC ||
       code.size() > (size_t)VM_MAXCODE ||
       outs.size() > (size_t)VM_MAXOUT)
-    return fail(c, DFX_EUNSUPPORTED, "fused pass exceeds the kernel's stream/op limits");
+    return fail_limit(c, "fused pass exceeds the kernel's stream/op limits");
 
   bool heavy = false, has_pow = false;
   for (auto& I : code) { heavy = heavy || heavy_op(I.op); has_pow = has_pow || pow_op(I.op); }
@@ -911,7 +918,7 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     if (!ok) { tier = TIER_TRANS16; ok = allocate(VM_NREG, stream_bucket(nin, tier)); }
   }
   if (!ok) { tier = TIER_POW; ok = allocate(VM_NREG, stream_bucket(nin, tier)); }
-  if (!ok) return fail(c, DFX_EUNSUPPORTED, "fused pass needs more than 16 live values");
+  if (!ok) return fail_limit(c, "fused pass needs more than 16 live values");
   out.tier = tier;
   out.nreg = 0;
   for (auto& v : vals) out.nreg = std::max(out.nreg, v.reg + 1);
@@ -1304,10 +1311,18 @@ static int dispatch_one(Ctx& c, bool may_grow = false) {
       c.window_cur = (int)std::min<int64_t>(2 * (int64_t)c.window_cur, c.cfg.auto_window);
       return DFX_OK;
     }
-    std::set<int64_t> temps;
-    if (c.cfg.fuse) temps = temporaries(c, f);
-    owned.reset(new Plan());
-    int rc = build_plan(c, f, temps, order, *owned);
+    // A group one kernel cannot hold is cut short: every prefix of a fusible
+    // prefix is fusible, so the longest prefix that lowers is dispatched and
+    // the rest stays in the window.
+    int rc;
+    for (int g = f;; --g) {
+      std::set<int64_t> temps;
+      if (c.cfg.fuse) temps = temporaries(c, g);
+      owned.reset(new Plan());
+      c.over_limit = false;
+      rc = build_plan(c, g, temps, order, *owned);
+      if (!(rc == DFX_EUNSUPPORTED && c.over_limit && g > 1)) break;
+    }
     if (rc) {
       if (!(c.analysis_only && rc == DFX_EUNSUPPORTED)) return rc;
       owned->passes.clear();

@@ -137,6 +137,7 @@ struct Ctx {
   dfx_config cfg{};
   hipStream_t stream = nullptr;
   bool analysis_only = false;
+  bool over_limit = false;  // the last lowering failed on a kernel capacity limit
   std::string err;
 
   int64_t next_store = 1;

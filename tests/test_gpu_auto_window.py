@@ -6,7 +6,8 @@ import pytest
 
 import paper_2406_18109_amd as dfx
 import synth
-from gpu_util import bs_run, note, upload
+from gpu_util import bs_run, note, rel_err_floor, upload
+from oracle import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
@@ -41,3 +42,21 @@ def test_auto_window_cg_bit_identical():
         c.close()
     (ra, xa, ga), (rf, xf, gf) = out
     assert ga == gf and ra == rf and np.array_equal(xa, xf)
+
+
+def test_window_16_black_scholes_split_bit_identical():
+    """A fixed window of 16 cuts the Black-Scholes group to what one kernel
+    holds (6, 6, 6, then the last 10 at the flush); every op still rounds on
+    its own, so the results equal the one-pass window's bit for bit."""
+    n = 3 * 4096 + 77
+    note("window 16: black-scholes split n=%d" % n)
+    c = dfx.Context(device=0, window_size=16)
+    (S, K, T, r, sig, rv), call_s, put_s = bs_run(c, n)
+    assert [g["prefix_len"] for g in c.groups()] == [6, 6, 6, 10]
+    c.close()
+    c = dfx.Context(device=0, window_size=64)
+    _, call_f, put_f = bs_run(c, n)
+    c.close()
+    assert np.array_equal(call_s, call_f) and np.array_equal(put_s, put_f)
+    oc, op = wl.black_scholes(S, K, T, r, sig, rv)
+    assert rel_err_floor(call_s, oc) <= 1e-12 and rel_err_floor(put_s, op) <= 1e-12
