@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdfx.so")
+# DFX_LIB names another build of the same library (the sanitizer build of
+# the host code that the CPU tests use); by default the in-tree libdfx.so
+LIB_PATH = os.environ.get("DFX_LIB") or os.path.join(_HERE, "libdfx.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOMEM_BUDGET, EBREAKDOWN, EMAXITER, ENOTFOUND, EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9

@@ -71,5 +71,54 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host code with AddressSanitizer and UndefinedBehaviorSanitizer, for the
+# CPU tests of the host logic (analysis-only contexts): the host sources are
+# compiled by g++ and linked with the kernel objects of the last build().
+# Python is not instrumented, so the runtime must be preloaded
+# (sanitizer_env).  Output: _build/libdfx_san.so.
+SAN_OUT = os.path.join(BUILD, "libdfx_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized() -> str:
+    kernels = [os.path.join(BUILD, src + ".o") for src, device in SOURCES if device]
+    if not all(os.path.exists(k) for k in kernels):
+        build()
+    objs = []
+    for src, device in SOURCES:
+        if device:
+            continue
+        obj = os.path.join(BUILD, src + ".san.o")
+        cmd = (["g++", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-D__HIP_PLATFORM_AMD__",
+                "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include")] + SAN_FLAGS +
+               ["-c", os.path.join(CSRC, src), "-o", obj])
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("sanitizer compile failed: " + src)
+        objs.append(obj)
+    cmd = (["g++", "-shared", "-fPIC", "-pthread"] + SAN_FLAGS + ["-o", SAN_OUT] + objs + kernels +
+           ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("sanitizer link failed")
+    return SAN_OUT
+
+
+def sanitizer_env() -> dict:
+    """Environment that loads the sanitizer build into an uninstrumented Python."""
+    rt = []
+    for name in ("libasan.so", "libubsan.so"):
+        path = subprocess.run(["g++", "-print-file-name=" + name], capture_output=True, text=True).stdout.strip()
+        if not os.path.isabs(path):
+            raise RuntimeError("sanitizer runtime not found: " + name)
+        rt.append(path)
+    env = dict(os.environ)
+    env.update(DFX_LIB=SAN_OUT, LD_PRELOAD=" ".join(rt), ASAN_OPTIONS="detect_leaks=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    return env
+
+
 if __name__ == "__main__":
     build(verbose=True)
