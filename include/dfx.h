@@ -236,7 +236,10 @@ int dfx_stats_reset(dfx_ctx* ctx);
  * wrote it: another build's file, a wrong magic, a checksum mismatch or a
  * truncated body is rejected with DFX_EINVAL and nothing is added; a
  * missing file gives DFX_ENOTFOUND.  load needs memo = 1 and fuse = 1
- * (DFX_ESTATE).  A pass saved while its launch shape was being tuned is
+ * (DFX_ESTATE) and is refused while a graph is being recorded (DFX_ESTATE).
+ * Loaded plans get their device workspaces at load, so a graph can be
+ * recorded from them with no eager run first.  A pass saved while its
+ * launch shape was being tuned is
  * stored with the default shape.  The file is trusted input: it is meant to
  * be one that dfx_plan_cache_save wrote. */
 int dfx_plan_cache_save(dfx_ctx* ctx, const char* path, int64_t* n_saved);

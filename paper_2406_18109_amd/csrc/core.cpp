@@ -1738,6 +1738,7 @@ int dfx_plan_cache_save(dfx_ctx* c, const char* path, int64_t* n_saved) {
 int dfx_plan_cache_load(dfx_ctx* c, const char* path, int64_t* n_loaded) {
   if (!c || !path) return DFX_EINVAL;
   if (!c->cfg.memo || !c->cfg.fuse) return fail(*c, DFX_ESTATE, "the plan cache needs memo = 1 and fuse = 1");
+  if (c->capturing) return fail(*c, DFX_ESTATE, "not while a graph is being recorded");
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(*c, DFX_ENOTFOUND, std::string("cannot read ") + path);
   std::string data;
@@ -1780,8 +1781,17 @@ int dfx_plan_cache_load(dfx_ctx* c, const char* path, int64_t* n_loaded) {
   }
   if (!rd.ok || rd.p != rd.e) return fail(*c, DFX_EINVAL, "malformed plan cache");
   int64_t added = 0;
-  for (auto& kv : got_plans)
-    if (c->memo.size() < 4096 && c->memo.emplace(std::move(kv.first), std::move(kv.second)).second) ++added;
+  for (auto& kv : got_plans) {
+    if (c->memo.size() >= 4096) break;
+    auto ins = c->memo.emplace(std::move(kv.first), std::move(kv.second));
+    if (!ins.second) continue;
+    ++added;
+    // workspaces now, so that a graph can be recorded before any eager run
+    for (PassPlan& q : ins.first->second->passes) {
+      const int rc = ensure_workspace(*c, q);
+      if (rc) return rc;
+    }
+  }
   if (n_loaded) *n_loaded = added;
   return DFX_OK;
 }

@@ -42,3 +42,40 @@ def test_loaded_plans_bit_identical(tmp_path):
     assert st["memo_misses"] == 0
     for x, y in zip(ra, rb):
         assert np.array_equal(x, y)
+
+
+def test_capture_from_loaded_plans_without_eager_run(tmp_path):
+    """A context that loads the cache records a CG iteration as a graph
+    straight away (plans and workspaces come from the load); three replays
+    equal three eager iterations of the saving context bit for bit."""
+    path = str(tmp_path / "plans.bin")
+    m = 40
+    rowptr, col, val = synth.poisson_csr(m, 2)
+    b = synth.rhs(m * m, 4140)
+    note("plan cache: eager cg %d^2, save" % m)
+    a = dfx.Context(device=0, window_size=16)
+    cg = dfx.apps.CG(a, *[upload(a, v) for v in (rowptr, col, val, b)], m * m)
+    rho_a = [float(a.store_read(cg.rho, [], "f64"))]
+    for _ in range(3):
+        cg.iteration()
+        rho_a.append(float(a.store_read(cg.rho, [], "f64")))
+    x_a = a.store_read(cg.x, [m * m], "f64")
+    a.plan_cache_save(path)
+    a.close()
+    note("plan cache: load, capture with no eager iteration")
+    c = dfx.Context(device=0, window_size=16)
+    c.plan_cache_load(path)
+    cg = dfx.apps.CG(c, *[upload(c, v) for v in (rowptr, col, val, b)], m * m)
+    rho_c = [float(c.store_read(cg.rho, [], "f64"))]
+    c.graph_begin()
+    cg.iteration()
+    g = c.graph_end()
+    for _ in range(3):
+        c.graph_launch(g)
+        rho_c.append(float(c.store_read(cg.rho, [], "f64")))
+    x_c = c.store_read(cg.x, [m * m], "f64")
+    st = c.stats()
+    c.graph_destroy(g)
+    c.close()
+    assert st["memo_misses"] == 0
+    assert rho_c == rho_a and np.array_equal(x_c, x_a)
