@@ -46,8 +46,11 @@ def test_loaded_plans_bit_identical(tmp_path):
 
 def test_capture_from_loaded_plans_without_eager_run(tmp_path):
     """A context that loads the cache records a CG iteration as a graph
-    straight away (plans and workspaces come from the load); three replays
-    equal three eager iterations of the saving context bit for bit."""
+    with no eager iteration first: plans and their workspaces come from the
+    load, and the iteration's work stores get their memory from host writes
+    (stores are allocated at their first write; a recording cannot
+    allocate).  Three replays equal three eager iterations of the saving
+    context bit for bit."""
     path = str(tmp_path / "plans.bin")
     m = 40
     rowptr, col, val = synth.poisson_csr(m, 2)
@@ -67,6 +70,10 @@ def test_capture_from_loaded_plans_without_eager_run(tmp_path):
     c.plan_cache_load(path)
     cg = dfx.apps.CG(c, *[upload(c, v) for v in (rowptr, col, val, b)], m * m)
     rho_c = [float(c.store_read(cg.rho, [], "f64"))]
+    # overwritten or started afresh by the iteration, so the values do not matter
+    c.store_write(cg.q, np.zeros(m * m))
+    for s in (cg.pq, cg.alpha, cg.rho_new, cg.beta):
+        c.store_write(s, np.zeros(()))
     c.graph_begin()
     cg.iteration()
     g = c.graph_end()
