@@ -59,3 +59,37 @@ def test_recurrence_residual_is_true_residual():
         xk, _ = wl.bicgstab(rowptr, col, val, b, k)
         true = b - A @ xk
         assert abs(hist[k] - np.dot(true, true)) <= 1e-9 * hist[k] + 1e-28 * hist[0], k
+
+
+def _planted(old, new):
+    """The oracle's bicgstab with one plausible mistake written into it."""
+    import inspect
+    import textwrap
+    from oracle import cnum
+    src = textwrap.dedent(inspect.getsource(wl.bicgstab))
+    assert src.count(old) == 1, old
+    ns = {"np": np, "cnum": cnum}
+    exec(compile(src.replace(old, new), "<planted>", "exec"), ns)
+    return ns["bicgstab"]
+
+
+def test_pins_catch_planted_mistakes():
+    """Each mistake (a dropped term, a wrong sign, a dropped factor, a
+    swapped operand) makes the SciPy-iterate pin fail."""
+    rowptr, col, val = synth.convdiff_csr(12, 2)
+    b = synth.rhs(144, 4001)
+    its = []
+    spla.bicgstab(_mat(rowptr, col, val), b, rtol=0.0, atol=0.0, maxiter=4,
+                  callback=lambda xk: its.append(xk.copy()))
+    mistakes = [("x = (x + alpha * p) + omega * s", "x = x + alpha * p"),
+                ("r = s - omega * t", "r = s + omega * t"),
+                ("beta = (rho_new / rho) * (alpha / omega)", "beta = rho_new / rho"),
+                ("omega = cnum.fsum_prod(t, s) / cnum.fsum_prod(t, t)",
+                 "omega = cnum.fsum_prod(t, s) / cnum.fsum_prod(s, s)")]
+    for old, new in mistakes:
+        bad = _planted(old, new)
+        errs = []
+        for j in range(1, 5):
+            x, _ = bad(rowptr, col, val, b, j)
+            errs.append(np.max(np.abs(x - its[j - 1])) / np.max(np.abs(its[j - 1])))
+        assert max(errs) > 1e-6, (new, errs)
