@@ -26,6 +26,11 @@ host C library (oracle/cnum.c); reductions are exactly rounded.
                  evaluation's task-count table lists; the paper gives no
                  formula, so the published recurrence is used with x0 = 0
                  and the shadow residual r^ = r0 = b
+  gmg            geometric multigrid V-cycles (the evaluation's GMG
+                 application; its source is not given, so the textbook
+                 cycle is used: weighted-Jacobi smoothing, full-weighting
+                 restriction, bilinear prolongation, rediscretised coarse
+                 operators, smoothing sweeps on the coarsest grid)
 """
 from __future__ import annotations
 
@@ -200,5 +205,45 @@ def bicgstab(rowptr, col, val, b, iters):
         omega = cnum.fsum_prod(t, s) / cnum.fsum_prod(t, t)
         x = (x + alpha * p) + omega * s
         r = s - omega * t
+        hist.append(cnum.fsum_prod(r, r))
+    return x, hist
+
+
+def gmg(levels, b, cycles, nu1=2, nu2=2, nu_c=30):
+    """V-cycles from x0 = 0.  levels[l] = (A, w, R, P): the level's CSR
+    operator, its smoothing weight (omega / diagonal), restriction to level
+    l+1 and prolongation from it (None on the coarsest level).  A smoothing
+    sweep is q = A x, r = b - q, x = x + w r.  One cycle on level l: nu1
+    sweeps; r = b - A x; b' = R r; x' = the cycle on level l+1 from 0;
+    x = x + P x'; nu2 sweeps.  The coarsest level does nu_c sweeps.
+    Returns (x, history) with history[k] = |b - A x_k|^2 (k = 0..cycles)."""
+    b = np.asarray(b, dtype=np.float64)
+
+    def mv(M, v):
+        return cnum.spmv(M[0], M[1], M[2], v)
+
+    def smooth(l, bl, x, sweeps):
+        A, w = levels[l][0], levels[l][1]
+        for _ in range(sweeps):
+            r = bl - mv(A, x)
+            x = x + w * r
+        return x
+
+    def cycle(l, bl, x):
+        if l == len(levels) - 1:
+            return smooth(l, bl, x, nu_c)
+        A, _, R, P = levels[l]
+        x = smooth(l, bl, x, nu1)
+        r = bl - mv(A, x)
+        bc = mv(R, r)
+        xc = cycle(l + 1, bc, np.zeros(R[0].size - 1))
+        x = x + mv(P, xc)
+        return smooth(l, bl, x, nu2)
+
+    x = np.zeros_like(b)
+    hist = [cnum.fsum_prod(b, b)]
+    for _ in range(cycles):
+        x = cycle(0, b, x)
+        r = b - mv(levels[0][0], x)
         hist.append(cnum.fsum_prod(r, r))
     return x, hist

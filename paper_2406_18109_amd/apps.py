@@ -220,3 +220,81 @@ class BiCGSTAB:
         # the next iteration's rho' = r^.r, issued here so that it joins this
         # window (also when one iteration is captured as a graph)
         c.submit("dot", d, [(rhat, T, "R"), (r, T, "R"), (self.rho_new, N, "Rd")], (1,))
+
+
+class GMG:
+    """Geometric multigrid V-cycles as a NumPy/SciPy program issues them:
+    every operator application, restriction and prolongation is an SpMV
+    task with its own CSR matrix, every vector update an elementwise task.
+    `levels[l]` = (A, w, R, P) of store handles and the level's smoothing
+    weight (R = P = None on the coarsest level); `sizes[l]` its unknowns.
+    A sweep is q = A x, r = b - q, x = x + w r; a cycle on level l is nu1
+    sweeps, b' = R (b - A x), x' = the cycle on level l+1 from 0,
+    x = x + P x', nu2 sweeps; the coarsest level does nu_c sweeps.  After
+    each cycle rr = |b - A x|^2."""
+
+    def __init__(self, ctx: Context, levels, sizes, b, nu1=2, nu2=2, nu_c=30):
+        c = ctx
+        self.ctx, self.levels, self.sizes = c, levels, sizes
+        self.nu1, self.nu2, self.nu_c = nu1, nu2, nu_c
+        self.none = c.part_none()
+        self.tile = [c.part_tiling([n]) for n in sizes]
+        self.img = {}
+        for A, _, R, P in levels:
+            for M in (A, R, P):
+                if M is not None:
+                    self.img[M[1]] = c.part_image(M[1], self.none)
+        vec = lambda n: c.store_create([n], "f64")
+        self.x = [vec(n) for n in sizes]
+        self.b = [b] + [vec(n) for n in sizes[1:]]
+        self.rr = c.store_create([], "f64")
+        c.submit("fill", [1], [(self.x[0], self.tile[0], "W")], (0.0,))
+
+    def _spmv(self, M, src, dst, l_dst):
+        c, N = self.ctx, self.none
+        c.submit("spmv_csr", [1], [(M[0], N, "R"), (M[1], N, "R"), (M[2], N, "R"),
+                                   (src, self.img[M[1]], "R"), (dst, self.tile[l_dst], "W")])
+
+    def _residual(self, l):
+        c, T = self.ctx, self.tile[l]
+        q, r = c.store_create([self.sizes[l]], "f64"), c.store_create([self.sizes[l]], "f64")
+        self._spmv(self.levels[l][0], self.x[l], q, l)
+        c.submit("sub", [1], [(self.b[l], T, "R"), (q, T, "R"), (r, T, "W")])
+        c.store_release(q)
+        return r
+
+    def _smooth(self, l, sweeps):
+        c, T, w = self.ctx, self.tile[l], self.levels[l][1]
+        for _ in range(sweeps):
+            r = self._residual(l)
+            t = c.store_create([self.sizes[l]], "f64")
+            c.submit("mul_imm", [1], [(r, T, "R"), (t, T, "W")], (w,))
+            c.submit("add", [1], [(self.x[l], T, "R"), (t, T, "R"), (self.x[l], T, "W")])
+            c.store_release(r)
+            c.store_release(t)
+
+    def _cycle(self, l):
+        c = self.ctx
+        if l == len(self.levels) - 1:
+            self._smooth(l, self.nu_c)
+            return
+        _, _, R, P = self.levels[l]
+        T = self.tile[l]
+        self._smooth(l, self.nu1)
+        r = self._residual(l)
+        self._spmv(R, r, self.b[l + 1], l + 1)
+        c.store_release(r)
+        c.submit("fill", [1], [(self.x[l + 1], self.tile[l + 1], "W")], (0.0,))
+        self._cycle(l + 1)
+        e = c.store_create([self.sizes[l]], "f64")
+        self._spmv(P, self.x[l + 1], e, l)
+        c.submit("add", [1], [(self.x[l], T, "R"), (e, T, "R"), (self.x[l], T, "W")])
+        c.store_release(e)
+        self._smooth(l, self.nu2)
+
+    def cycle(self):
+        c, T, N = self.ctx, self.tile[0], self.none
+        self._cycle(0)
+        r = self._residual(0)
+        c.submit("dot", [1], [(r, T, "R"), (r, T, "R"), (self.rr, N, "Rd")], (1,))
+        c.store_release(r)

@@ -140,6 +140,64 @@ def poisson_csr(m: int, dim: int):
 
 
 
+def _csr_from_rows(rows, ncols):
+    rowptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([len(r) for r in rows], out=rowptr[1:])
+    col = np.array([c for r in rows for c, _ in sorted(r)], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in sorted(r)], dtype=np.float64)
+    return rowptr.astype(np.int32), col, val
+
+
+def restriction_csr(mc: int):
+    """Full weighting from the (2 mc + 1)^2 interior grid to the mc^2 one
+    (x fastest, Dirichlet boundary): coarse point (I, J) sits on fine point
+    (2I+1, 2J+1) with weight 1/4, its 4 edge neighbours 1/8 and 4 corners
+    1/16 (all exact).  Shape mc^2 x (2 mc + 1)^2."""
+    mf = 2 * mc + 1
+    rows = []
+    for J in range(mc):
+        for I in range(mc):
+            fi, fj = 2 * I + 1, 2 * J + 1
+            rows.append([((fj + dj) * mf + fi + di, (2 - abs(di)) * (2 - abs(dj)) / 16.0)
+                         for dj in (-1, 0, 1) for di in (-1, 0, 1)])
+    return _csr_from_rows(rows, mf * mf)
+
+
+def prolongation_csr(mc: int):
+    """Bilinear interpolation from the mc^2 grid to the (2 mc + 1)^2 one:
+    4 times the transpose of restriction_csr (weights 1, 1/2, 1/4)."""
+    rp, col, val = restriction_csr(mc)
+    mf = 2 * mc + 1
+    rows = [[] for _ in range(mf * mf)]
+    for r in range(mc * mc):
+        for k in range(rp[r], rp[r + 1]):
+            rows[col[k]].append((r, 4.0 * val[k]))
+    return _csr_from_rows(rows, mc * mc)
+
+
+def gmg_levels(m0: int, nlev: int, omega: float = 0.8):
+    """The multigrid hierarchy of the m0^2 Poisson problem (m0 = 2^k - 1):
+    level l has side m_l = (m_{l-1} - 1) / 2 and operator poisson_csr(m_l)
+    scaled by 4^-l (the 5-point operator rediscretised on the coarser grid,
+    in units of the finest h^2; every value stays exact), smoothing weight
+    omega / (4 4^-l), and the transfers to and from level l+1.  Returns
+    [(A, w, R, P)] with R = P = None on the coarsest level."""
+    out, m = [], m0
+    for l in range(nlev):
+        rp, col, val = poisson_csr(m, 2)
+        A = (rp, col, val * 0.25 ** l)
+        w = omega / (4.0 * 0.25 ** l)
+        if l < nlev - 1:
+            if m % 2 == 0 or m < 3:
+                raise ValueError("side must be 2^k - 1 on every level but the last")
+            mc = (m - 1) // 2
+            out.append((A, w, restriction_csr(mc), prolongation_csr(mc)))
+            m = mc
+        else:
+            out.append((A, w, None, None))
+    return out
+
+
 def convdiff_csr(m: int, dim: int, c: float = 0.5):
     """A nonsymmetric variant of poisson_csr: first-order upwind convection
     along x, so the diagonal is 2*dim + c and the west neighbour -1 - c (c
