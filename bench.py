@@ -9,7 +9,7 @@ group executed as one kernel.  Inputs are resident in HBM before timing.
 Printed: one JSON line with the headline (fused algorithmic HBM GB/s), the
 roofline of the dominant kernel, the CPU oracle timed on a bounded sample,
 and the other legs of the metric (unfused GB/s, FP32, Jacobi stencil, CG
-and BiCGSTAB iterations/s, and the continuous-batching server: its closed-loop saturation
+and BiCGSTAB iterations/s, multigrid cycles/s, and the continuous-batching server: its closed-loop saturation
 solves/s, then p50/p99 latency with Poisson arrivals at 0.5, 0.8 and 0.95 of
 saturation, the 0.8 point over the whole 4096-request stream) under "legs".
 Progress goes to stderr.
@@ -197,6 +197,49 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg"):
     return out
 
 
+def gmg_leg(torch, dfx, synth, np, m, nlev, cycles, fuse, graph):
+    """Multigrid V(2,2) cycles on the m^2 Poisson problem over nlev levels;
+    with graph, one whole cycle is recorded and replayed."""
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
+    levels = synth.gmg_levels(m, nlev)
+
+    def up(a):
+        s = c.store_create(list(a.shape), "i32" if a.dtype == np.int32 else "f64")
+        c.store_write(s, a)
+        return s
+    lev = [(tuple(up(a) for a in A), w, None if R is None else tuple(up(a) for a in R),
+            None if P is None else tuple(up(a) for a in P)) for A, w, R, P in levels]
+    sizes = [A[0].size - 1 for A, _, _, _ in levels]
+    del levels
+    g = dfx.apps.GMG(c, lev, sizes, up(synth.rhs(m * m, synth.GMG_SEED)))
+    c.sync()
+    g.cycle()
+    c.sync()
+    gid = None
+    if graph:
+        c.graph_begin()
+        g.cycle()
+        gid = c.graph_end()
+    c.sync()
+    c.stats_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        if gid is not None:
+            c.graph_launch(gid)
+        else:
+            g.cycle()
+    c.sync()
+    dt = (time.perf_counter() - t0) / cycles
+    st = c.stats()
+    out = {"cycles_per_s": 1.0 / dt, "ms_per_cycle": dt * 1e3, "alg_bytes_per_cycle": st["alg_bytes"] / cycles,
+           "gbs": st["alg_bytes"] / cycles / dt / 1e9, "launches_per_cycle": st["launches"] / cycles}
+    if gid is not None:
+        c.graph_destroy(gid)
+    c.close()
+    return out
+
+
 def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0, mats=None):
     """Continuous-batching server on the first `count` requests of the serving
     stream: 2-D Poisson solves, side uniform in [32, 512], tol 1e-8, Poisson
@@ -326,7 +369,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="enable the library's launch-shape tuner (warm-ups extended to 8 executions)")
     ap.add_argument("--legs", default="all",
-                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,bicgstab256,serve")
+                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,bicgstab256,gmg,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="fixed Poisson arrival rate; default: a saturation run, then 0.5/0.8/0.95 of it")
@@ -360,9 +403,9 @@ def main():
         print(json.dumps(out))
         return
     # legs: "all" (the default line), "headline", or a comma-separated list of
-    # bs_f64, bs_f32, jacobi, cg64, cg256, bicgstab256, serve
+    # bs_f64, bs_f32, jacobi, cg64, cg256, bicgstab256, gmg, serve
     if args.legs == "all":
-        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "bicgstab256", "serve"}
+        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "bicgstab256", "gmg", "serve"}
     elif args.legs == "headline":
         sel = set()
     else:
@@ -402,6 +445,12 @@ def main():
         legs["bicgstab256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 6, False, False, "bicgstab")
         legs["bicgstab256_fused_graph"]["speedup_vs_unfused"] = (legs["bicgstab256_unfused"]["ms_per_iter"] /
                                                                  legs["bicgstab256_fused_graph"]["ms_per_iter"])
+    if "gmg" in sel:
+        log("gmg 1023^2, 9 levels")
+        legs["gmg1023_fused_graph"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 10, True, True)
+        legs["gmg1023_unfused"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 3, False, False)
+        legs["gmg1023_fused_graph"]["speedup_vs_unfused"] = (legs["gmg1023_unfused"]["ms_per_cycle"] /
+                                                             legs["gmg1023_fused_graph"]["ms_per_cycle"])
     if "serve" in sel:
         log("serving: %d CG solves, %s" % (args.serve_requests, "load sweep" if args.serve_rate is None
                                               else "Poisson arrivals at %.0f/s" % args.serve_rate))

@@ -231,7 +231,10 @@ class GMG:
     A sweep is q = A x, r = b - q, x = x + w r; a cycle on level l is nu1
     sweeps, b' = R (b - A x), x' = the cycle on level l+1 from 0,
     x = x + P x', nu2 sweeps; the coarsest level does nu_c sweeps.  After
-    each cycle rr = |b - A x|^2."""
+    each cycle rr = |b - A x|^2.  The residual that crosses windows and the
+    smoothing weight live in stores of their own per level, so a cycle
+    allocates nothing once one has run (it can be recorded as a graph);
+    x + w r is an axpy with the weight as a 0-d store."""
 
     def __init__(self, ctx: Context, levels, sizes, b, nu1=2, nu2=2, nu_c=30):
         c = ctx
@@ -247,6 +250,12 @@ class GMG:
         vec = lambda n: c.store_create([n], "f64")
         self.x = [vec(n) for n in sizes]
         self.b = [b] + [vec(n) for n in sizes[1:]]
+        self.r = [vec(n) for n in sizes]
+        self.w = []
+        for _, w, _, _ in levels:
+            h = c.store_create([], "f64")
+            c.submit("fill", [], [(h, self.none, "W")], (w,))
+            self.w.append(h)
         self.rr = c.store_create([], "f64")
         c.submit("fill", [1], [(self.x[0], self.tile[0], "W")], (0.0,))
 
@@ -257,21 +266,17 @@ class GMG:
 
     def _residual(self, l):
         c, T = self.ctx, self.tile[l]
-        q, r = c.store_create([self.sizes[l]], "f64"), c.store_create([self.sizes[l]], "f64")
+        q = c.store_create([self.sizes[l]], "f64")
         self._spmv(self.levels[l][0], self.x[l], q, l)
-        c.submit("sub", [1], [(self.b[l], T, "R"), (q, T, "R"), (r, T, "W")])
+        c.submit("sub", [1], [(self.b[l], T, "R"), (q, T, "R"), (self.r[l], T, "W")])
         c.store_release(q)
-        return r
+        return self.r[l]
 
     def _smooth(self, l, sweeps):
-        c, T, w = self.ctx, self.tile[l], self.levels[l][1]
+        c, T, N = self.ctx, self.tile[l], self.none
         for _ in range(sweeps):
             r = self._residual(l)
-            t = c.store_create([self.sizes[l]], "f64")
-            c.submit("mul_imm", [1], [(r, T, "R"), (t, T, "W")], (w,))
-            c.submit("add", [1], [(self.x[l], T, "R"), (t, T, "R"), (self.x[l], T, "W")])
-            c.store_release(r)
-            c.store_release(t)
+            c.submit("axpy", [1], [(self.w[l], N, "R"), (r, T, "R"), (self.x[l], T, "RW")], (1.0,))
 
     def _cycle(self, l):
         c = self.ctx
@@ -283,7 +288,6 @@ class GMG:
         self._smooth(l, self.nu1)
         r = self._residual(l)
         self._spmv(R, r, self.b[l + 1], l + 1)
-        c.store_release(r)
         c.submit("fill", [1], [(self.x[l + 1], self.tile[l + 1], "W")], (0.0,))
         self._cycle(l + 1)
         e = c.store_create([self.sizes[l]], "f64")
@@ -297,4 +301,3 @@ class GMG:
         self._cycle(0)
         r = self._residual(0)
         c.submit("dot", [1], [(r, T, "R"), (r, T, "R"), (self.rr, N, "Rd")], (1,))
-        c.store_release(r)

@@ -140,39 +140,36 @@ def poisson_csr(m: int, dim: int):
 
 
 
-def _csr_from_rows(rows, ncols):
-    rowptr = np.zeros(len(rows) + 1, dtype=np.int64)
-    np.cumsum([len(r) for r in rows], out=rowptr[1:])
-    col = np.array([c for r in rows for c, _ in sorted(r)], dtype=np.int32)
-    val = np.array([v for r in rows for _, v in sorted(r)], dtype=np.float64)
-    return rowptr.astype(np.int32), col, val
-
-
 def restriction_csr(mc: int):
     """Full weighting from the (2 mc + 1)^2 interior grid to the mc^2 one
     (x fastest, Dirichlet boundary): coarse point (I, J) sits on fine point
     (2I+1, 2J+1) with weight 1/4, its 4 edge neighbours 1/8 and 4 corners
-    1/16 (all exact).  Shape mc^2 x (2 mc + 1)^2."""
+    1/16 (all exact), columns ascending.  Shape mc^2 x (2 mc + 1)^2."""
     mf = 2 * mc + 1
-    rows = []
-    for J in range(mc):
-        for I in range(mc):
-            fi, fj = 2 * I + 1, 2 * J + 1
-            rows.append([((fj + dj) * mf + fi + di, (2 - abs(di)) * (2 - abs(dj)) / 16.0)
-                         for dj in (-1, 0, 1) for di in (-1, 0, 1)])
-    return _csr_from_rows(rows, mf * mf)
+    J, I = np.divmod(np.arange(mc * mc, dtype=np.int64), mc)
+    cols, vals = [], []
+    for dj in (-1, 0, 1):          # ascending fine row, then column: ascending index
+        for di in (-1, 0, 1):
+            cols.append((2 * J + 1 + dj) * mf + 2 * I + 1 + di)
+            vals.append(np.full(mc * mc, (2 - abs(di)) * (2 - abs(dj)) / 16.0))
+    col = np.stack(cols, axis=1).ravel().astype(np.int32)
+    val = np.stack(vals, axis=1).ravel()
+    rowptr = (np.arange(mc * mc + 1, dtype=np.int64) * 9).astype(np.int32)
+    return rowptr, col, val
 
 
 def prolongation_csr(mc: int):
     """Bilinear interpolation from the mc^2 grid to the (2 mc + 1)^2 one:
-    4 times the transpose of restriction_csr (weights 1, 1/2, 1/4)."""
+    4 times the transpose of restriction_csr (weights 1, 1/2, 1/4), columns
+    ascending."""
     rp, col, val = restriction_csr(mc)
     mf = 2 * mc + 1
-    rows = [[] for _ in range(mf * mf)]
-    for r in range(mc * mc):
-        for k in range(rp[r], rp[r + 1]):
-            rows[col[k]].append((r, 4.0 * val[k]))
-    return _csr_from_rows(rows, mc * mc)
+    rows = np.repeat(np.arange(mc * mc, dtype=np.int64), 9)
+    order = np.lexsort((rows, col.astype(np.int64)))    # by fine row, then coarse column
+    fr, cc, vv = col[order].astype(np.int64), rows[order], 4.0 * val[order]
+    rowptr = np.zeros(mf * mf + 1, dtype=np.int64)
+    np.cumsum(np.bincount(fr, minlength=mf * mf), out=rowptr[1:])
+    return rowptr.astype(np.int32), cc.astype(np.int32), vv
 
 
 def gmg_levels(m0: int, nlev: int, omega: float = 0.8):
@@ -218,6 +215,7 @@ def rhs(n: int, seed: int, stream: int = 0) -> np.ndarray:
 CG64_SEED = 2001
 CG256_SEED = 2002
 BICG256_SEED = 2003   # BiCGSTAB on the 256^3 convection-diffusion system
+GMG_SEED = 2004       # multigrid on the 1023^2 Poisson problem
 
 
 # --------------------------------------------------------------------------

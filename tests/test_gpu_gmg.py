@@ -41,3 +41,34 @@ def test_gmg_fused_unfused_oracle(m, nlev):
     assert rel_err_floor(x_f, xo) <= 1e-12
     for k, g in enumerate(rr_f):
         assert abs(g - ho[k + 1]) <= 1e-10 * ho[k + 1], k
+
+
+def test_gmg_1023_full_size_graph():
+    """The benchmarked size (1023^2, 9 levels), run as the bench runs it:
+    one eager cycle, then one cycle recorded as a graph and replayed."""
+    m, nlev = 1023, 9
+    note("gmg full size %d^2" % m)
+    levels = synth.gmg_levels(m, nlev)
+    b = synth.rhs(m * m, synth.GMG_SEED)
+    c = dfx.Context(device=0, window_size=16)
+    lev = [(tuple(upload(c, a) for a in A), w, None if R is None else tuple(upload(c, a) for a in R),
+            None if P is None else tuple(upload(c, a) for a in P)) for A, w, R, P in levels]
+    sizes = [A[0].size - 1 for A, _, _, _ in levels]
+    g = dfx.apps.GMG(c, lev, sizes, upload(c, b))
+    c.sync()
+    g.cycle()
+    rr = [float(c.store_read(g.rr, [], "f64"))]
+    c.graph_begin()
+    g.cycle()
+    gid = c.graph_end()
+    for _ in range(2):
+        c.graph_launch(gid)
+        rr.append(float(c.store_read(g.rr, [], "f64")))
+    x = c.store_read(g.x[0], [m * m], "f64")
+    c.graph_destroy(gid)
+    c.close()
+    note("gmg full size: oracle")
+    xo, ho = wl.gmg(levels, b, 3)
+    assert rel_err_floor(x, xo) <= 1e-12
+    for k, v in enumerate(rr):
+        assert abs(v - ho[k + 1]) <= 1e-10 * ho[k + 1], k
