@@ -21,7 +21,9 @@
  *   the last error is available from dfx_last_error(ctx).  A rejected call
  *   changes nothing (a rejected submit leaves the window as it was).  A
  *   context is used from one host thread at a time.  Host buffers passed in
- *   remain owned by the caller and are copied before the call returns.
+ *   remain owned by the caller and are copied before the call returns, with
+ *   one exception: the CSR arrays of a serving request are borrowed until
+ *   the request leaves the QUEUED state (dfx_csr_desc).
  *   Device memory of stores is owned by the library (allocated through the
  *   configured callbacks, default a stream-ordered hipMallocAsync pool),
  *   except for stores made with dfx_store_wrap, whose memory is borrowed and
@@ -284,7 +286,9 @@ typedef struct {
 } dfx_serve_cfg;
 
 /* Host CSR arrays: validated and referenced (not copied) by submit; they must
- * stay valid until the solve leaves the QUEUED state. */
+ * stay valid, unchanged, until the solve leaves the QUEUED state.  The solve
+ * is reported QUEUED until the copies of its arrays to the device have
+ * completed, so a status of RUNNING or later means they may be freed. */
 typedef struct {
   int64_t n;
   int64_t nnz;

@@ -15,8 +15,12 @@
  *    the rounded products x_i*y_i), computed with Shewchuk's
  *    non-overlapping-partials method ("Adaptive Precision Floating-Point
  *    Arithmetic and Fast Robust Geometric Predicates", 1997) with a final
- *    round-half-even correction.  This is the reduction privilege's sum
- *    (section 3.2) with no rounding-order choice left.
+ *    round-half-even correction.  The partials loop and the half-even
+ *    correction follow the way CPython's math.fsum applies the method
+ *    (Raymond Hettinger's msum recipe, with its final correction across the
+ *    remaining partials); the tests check this sum against math.fsum.
+ *    This is the reduction privilege's sum (section 3.2) with no
+ *    rounding-order choice left.
  */
 #include <math.h>
 #include <stdint.h>

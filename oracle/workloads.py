@@ -26,11 +26,11 @@ host C library (oracle/cnum.c); reductions are exactly rounded.
                  evaluation's task-count table lists; the paper gives no
                  formula, so the published recurrence is used with x0 = 0
                  and the shadow residual r^ = r0 = b
-  gmg            geometric multigrid V-cycles (the evaluation's GMG
-                 application; its source is not given, so the textbook
-                 cycle is used: weighted-Jacobi smoothing, full-weighting
-                 restriction, bilinear prolongation, rediscretised coarse
-                 operators, smoothing sweeps on the coarsest grid)
+  pcg_gmg        the evaluation's GMG application: CG preconditioned by one
+                 multigrid V-cycle with injection restriction and a
+                 weighted-Jacobi smoother (gmg_operators builds the level
+                 operators from their one-dimensional factors; vcycle is the
+                 preconditioner)
 """
 from __future__ import annotations
 
@@ -209,41 +209,133 @@ def bicgstab(rowptr, col, val, b, iters):
     return x, hist
 
 
-def gmg(levels, b, cycles, nu1=2, nu2=2, nu_c=30):
-    """V-cycles from x0 = 0.  levels[l] = (A, w, R, P): the level's CSR
-    operator, its smoothing weight (omega / diagonal), restriction to level
-    l+1 and prolongation from it (None on the coarsest level).  A smoothing
-    sweep is q = A x, r = b - q, x = x + w r.  One cycle on level l: nu1
-    sweeps; r = b - A x; b' = R r; x' = the cycle on level l+1 from 0;
-    x = x + P x'; nu2 sweeps.  The coarsest level does nu_c sweeps.
-    Returns (x, history) with history[k] = |b - A x_k|^2 (k = 0..cycles)."""
-    b = np.asarray(b, dtype=np.float64)
+# ---------------------------------------------------------------------------
+# Geometric multigrid as the evaluation describes its GMG application: a
+# CG-based solver whose preconditioner is one V-cycle, with the injection
+# restriction operator and a weighted-Jacobi smoother.  What the paper leaves
+# open is read as follows: bilinear prolongation, the 5-point operator
+# rediscretised on each coarser grid, V(2,2) with weight 2/3, 8 smoothing
+# sweeps on the coarsest grid, and the V-cycle started from zero.
+# ---------------------------------------------------------------------------
+GMG_OMEGA = 2.0 / 3.0
 
-    def mv(M, v):
-        return cnum.spmv(M[0], M[1], M[2], v)
 
-    def smooth(l, bl, x, sweeps):
-        A, w = levels[l][0], levels[l][1]
-        for _ in range(sweeps):
-            r = bl - mv(A, x)
-            x = x + w * r
+def _csr(M):
+    """(rowptr int32, col int32, val float64) of a SciPy sparse matrix with
+    the columns of every row ascending and no stored zeros."""
+    import scipy.sparse as sp
+    M = sp.csr_matrix(M)
+    M.eliminate_zeros()
+    M.sort_indices()
+    return M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64)
+
+
+def gmg_operators(m0, nlev):
+    """The hierarchy of the m0 x m0 Dirichlet Poisson problem, m0 = 2^k - 1.
+
+    Level l has side m_l = (m_{l-1} - 1) / 2.  Each operator is built from
+    its one-dimensional factors (Kronecker products), unknowns numbered with
+    x fastest:
+      A_l = 4^-l (I (x) T + T (x) I), T = tridiag(-1, 2, -1) of size m_l: the
+            5-point operator of the finest grid's h^2 units rediscretised on
+            a grid of spacing 2^l h;
+      R_l = Ri (x) Ri, Ri[J, 2J+1] = 1: injection, coarse point (I, J) takes
+            the fine value at (2I+1, 2J+1);
+      P_l = Pi (x) Pi, Pi[2J, J] = Pi[2J+2, J] = 1/2, Pi[2J+1, J] = 1: bilinear
+            interpolation with zero Dirichlet values outside the grid.
+    Returns [(A, R, P)] as CSR triples (R = P = None on the coarsest level)."""
+    import scipy.sparse as sp
+    out, m = [], m0
+    for l in range(nlev):
+        T = sp.diags([-np.ones(m - 1), 2.0 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+        I = sp.identity(m)
+        A = (sp.kron(I, T) + sp.kron(T, I)) * (0.25 ** l)
+        if l == nlev - 1:
+            out.append((_csr(A), None, None))
+            break
+        if m % 2 == 0 or m < 3:
+            raise ValueError("side must be 2^k - 1 on every level but the last")
+        mc = (m - 1) // 2
+        Ri = sp.lil_matrix((mc, m))
+        Pi = sp.lil_matrix((m, mc))
+        for J in range(mc):
+            Ri[J, 2 * J + 1] = 1.0
+            Pi[2 * J, J] = 0.5
+            Pi[2 * J + 1, J] = 1.0
+            Pi[2 * J + 2, J] = 0.5
+        out.append((_csr(A), _csr(sp.kron(Ri, Ri)), _csr(sp.kron(Pi, Pi))))
+        m = mc
+    return out
+
+
+def gmg_weights(ops, omega=GMG_OMEGA):
+    """The smoothing weight of each level: omega over the operator's diagonal
+    (constant on a level), one rounded division."""
+    out = []
+    for (rp, col, val), _, _ in ops:
+        d = val[col == np.repeat(np.arange(rp.size - 1), np.diff(rp))]
+        assert np.all(d == d[0])
+        out.append(omega / float(d[0]))
+    return out
+
+
+def vcycle(ops, w, l, bl, nu1=2, nu2=2, nu_c=8):
+    """One V-cycle for A_l e = bl from e = 0.  A smoothing sweep is
+    q = A x, r = bl - q, x = x + w_l r.  Level l: nu1 sweeps; r = bl - A x;
+    b' = R r; x' = the cycle on level l+1; x = x + P x'; nu2 sweeps.  The
+    coarsest level does nu_c sweeps."""
+    A, R, P = ops[l]
+
+    def sweeps(x, k):
+        for _ in range(k):
+            q = cnum.spmv(A[0], A[1], A[2], x)
+            r = bl - q
+            x = x + w[l] * r
         return x
 
-    def cycle(l, bl, x):
-        if l == len(levels) - 1:
-            return smooth(l, bl, x, nu_c)
-        A, _, R, P = levels[l]
-        x = smooth(l, bl, x, nu1)
-        r = bl - mv(A, x)
-        bc = mv(R, r)
-        xc = cycle(l + 1, bc, np.zeros(R[0].size - 1))
-        x = x + mv(P, xc)
-        return smooth(l, bl, x, nu2)
+    x = np.zeros_like(bl)
+    if R is None:
+        return sweeps(x, nu_c)
+    x = sweeps(x, nu1)
+    q = cnum.spmv(A[0], A[1], A[2], x)
+    r = bl - q
+    bc = cnum.spmv(R[0], R[1], R[2], r)
+    xc = vcycle(ops, w, l + 1, bc, nu1, nu2, nu_c)
+    e = cnum.spmv(P[0], P[1], P[2], xc)
+    x = x + e
+    return sweeps(x, nu2)
 
+
+def pcg_gmg(ops, b, iters, nu1=2, nu2=2, nu_c=8, omega=GMG_OMEGA, precondition=True):
+    """Preconditioned CG from x0 = 0 with M = one V-cycle on the finest level
+    (precondition=False: M = I, which is plain CG).  One iteration, in this
+    order:
+      q = A p; pq = p.q; alpha = rho/pq; x = x + alpha p; r = r - alpha q;
+      rr = r.r; z = M r; rho' = r.z; beta = rho'/rho; rho = rho';
+      p = beta p; p = p + z
+    with z0 = M b, p0 = z0, rho0 = r0.z0.  Returns (x, history) where
+    history[k] = r_k . r_k (k = 0..iters)."""
+    A = ops[0][0]
+    w = gmg_weights(ops, omega)
+    b = np.asarray(b, dtype=np.float64)
+    M = (lambda r: vcycle(ops, w, 0, r, nu1, nu2, nu_c)) if precondition else (lambda r: r.copy())
     x = np.zeros_like(b)
-    hist = [cnum.fsum_prod(b, b)]
-    for _ in range(cycles):
-        x = cycle(0, b, x)
-        r = b - mv(levels[0][0], x)
+    r = b.copy()
+    z = M(r)
+    p = z.copy()
+    rho = cnum.fsum_prod(r, z)
+    hist = [cnum.fsum_prod(r, r)]
+    for _ in range(iters):
+        q = cnum.spmv(A[0], A[1], A[2], p)
+        pq = cnum.fsum_prod(p, q)
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
         hist.append(cnum.fsum_prod(r, r))
+        z = M(r)
+        rho_new = cnum.fsum_prod(r, z)
+        beta = rho_new / rho
+        rho = rho_new
+        p = beta * p
+        p = p + z
     return x, hist

@@ -33,6 +33,21 @@ BS_STREAM = [
 BS_SCALARS = ("sig", "rv", "r")
 
 
+def bs_drift(ctx: Context, r, sig, dtype="f64"):
+    """The drift term rv = r + sigma^2/2 that the pricing stream reads, formed
+    the way a NumPy program would before its pricing loop: three single tasks
+    on 0-d stores (sigma*sigma, times 0.5, plus r), each rounded in the
+    stores' dtype.  Returns the rv store."""
+    none = ctx.part_none()
+    sq, half, rv = (ctx.store_create([], dtype) for _ in range(3))
+    ctx.submit("mul", [], [(sig, none, "R"), (sig, none, "R"), (sq, none, "W")])
+    ctx.submit("mul_imm", [], [(sq, none, "R"), (half, none, "W")], (0.5,))
+    ctx.submit("add", [], [(r, none, "R"), (half, none, "R"), (rv, none, "W")])
+    ctx.store_release(sq)
+    ctx.store_release(half)
+    return rv
+
+
 def black_scholes(ctx: Context, S, K, T, r, sig, rv, n, dtype="f64", points=1):
     """Submit one pricing pass; returns (call, put) store handles.
 
@@ -223,20 +238,29 @@ class BiCGSTAB:
 
 
 class GMG:
-    """Geometric multigrid V-cycles as a NumPy/SciPy program issues them:
-    every operator application, restriction and prolongation is an SpMV
-    task with its own CSR matrix, every vector update an elementwise task.
-    `levels[l]` = (A, w, R, P) of store handles and the level's smoothing
-    weight (R = P = None on the coarsest level); `sizes[l]` its unknowns.
-    A sweep is q = A x, r = b - q, x = x + w r; a cycle on level l is nu1
-    sweeps, b' = R (b - A x), x' = the cycle on level l+1 from 0,
-    x = x + P x', nu2 sweeps; the coarsest level does nu_c sweeps.  After
-    each cycle rr = |b - A x|^2.  The residual that crosses windows and the
-    smoothing weight live in stores of their own per level, so a cycle
-    allocates nothing once one has run (it can be recorded as a graph);
-    x + w r is an axpy with the weight as a 0-d store."""
+    """The evaluation's GMG application as a SciPy program issues it: CG
+    preconditioned by one multigrid V-cycle, with the injection restriction
+    operator and a weighted-Jacobi smoother.  Every operator application,
+    restriction and prolongation is an SpMV task with its own CSR matrix;
+    every vector update an elementwise task.
 
-    def __init__(self, ctx: Context, levels, sizes, b, nu1=2, nu2=2, nu_c=30):
+    `levels[l]` = (A, diag, R, P): the level's CSR operator (store handles),
+    the value of its diagonal, and the transfers to and from level l+1
+    (R = P = None on the coarsest level); `sizes[l]` its unknowns.  The
+    smoothing weight of a level, omega / diag, is formed by single tasks at
+    set-up.  A sweep is q = A x, r = b - q, x = x + w r (an axpy with the
+    weight as a 0-d store); the V-cycle on level l starts from x = 0 and
+    does nu1 sweeps, b' = R (b - A x), the cycle on level l+1, x = x + P x',
+    nu2 sweeps; the coarsest level does nu_c sweeps.  The finest level's
+    right-hand side is CG's residual r and its x is CG's z = M r.  One CG
+    iteration:
+      q = A p; pq = p.q; alpha = rho/pq; x += alpha p; r -= alpha q;
+      rr = r.r; z = M r; rho' = r.z; beta = rho'/rho; rho = rho';
+      p = beta p; p = p + z
+    Per-level residual stores and the weights persist, so an iteration
+    allocates nothing once one has run (it can be recorded as a graph)."""
+
+    def __init__(self, ctx: Context, levels, sizes, b, nu1=2, nu2=2, nu_c=8, omega=2.0 / 3.0):
         c = ctx
         self.ctx, self.levels, self.sizes = c, levels, sizes
         self.nu1, self.nu2, self.nu_c = nu1, nu2, nu_c
@@ -248,16 +272,32 @@ class GMG:
                 if M is not None:
                     self.img[M[1]] = c.part_image(M[1], self.none)
         vec = lambda n: c.store_create([n], "f64")
-        self.x = [vec(n) for n in sizes]
-        self.b = [b] + [vec(n) for n in sizes[1:]]
-        self.r = [vec(n) for n in sizes]
+        sc = lambda: c.store_create([], "f64")
+        n0, T, N = sizes[0], self.tile[0], self.none
+        # CG state; the V-cycle's finest level solves into z from rhs r
+        self.x, self.r, self.z, self.p, self.q = (vec(n0) for _ in range(5))
+        self.pq, self.rho, self.rho_new, self.alpha, self.beta, self.rr = (sc() for _ in range(6))
+        self.lx = [self.z] + [vec(n) for n in sizes[1:]]
+        self.lb = [self.r] + [vec(n) for n in sizes[1:]]
+        self.lr = [vec(n) for n in sizes]
+        # w_l = omega / diag_l
         self.w = []
-        for _, w, _, _ in levels:
-            h = c.store_create([], "f64")
-            c.submit("fill", [], [(h, self.none, "W")], (w,))
+        om = sc()
+        c.submit("fill", [], [(om, N, "W")], (omega,))
+        for _, diag, _, _ in levels:
+            d, h = sc(), sc()
+            c.submit("fill", [], [(d, N, "W")], (diag,))
+            c.submit("div", [], [(om, N, "R"), (d, N, "R"), (h, N, "W")])
+            c.store_release(d)
             self.w.append(h)
-        self.rr = c.store_create([], "f64")
-        c.submit("fill", [1], [(self.x[0], self.tile[0], "W")], (0.0,))
+        c.store_release(om)
+        # x = 0; r = b; z = M r; p = z; rho = r.z; rr = r.r
+        c.submit("fill", [1], [(self.x, T, "W")], (0.0,))
+        c.submit("copy", [1], [(b, T, "R"), (self.r, T, "W")])
+        c.submit("dot", [1], [(self.r, T, "R"), (self.r, T, "R"), (self.rr, N, "Rd")], (1,))
+        self._cycle(0)
+        c.submit("copy", [1], [(self.z, T, "R"), (self.p, T, "W")])
+        c.submit("dot", [1], [(self.r, T, "R"), (self.z, T, "R"), (self.rho, N, "Rd")], (1,))
 
     def _spmv(self, M, src, dst, l_dst):
         c, N = self.ctx, self.none
@@ -267,37 +307,48 @@ class GMG:
     def _residual(self, l):
         c, T = self.ctx, self.tile[l]
         q = c.store_create([self.sizes[l]], "f64")
-        self._spmv(self.levels[l][0], self.x[l], q, l)
-        c.submit("sub", [1], [(self.b[l], T, "R"), (q, T, "R"), (self.r[l], T, "W")])
+        self._spmv(self.levels[l][0], self.lx[l], q, l)
+        c.submit("sub", [1], [(self.lb[l], T, "R"), (q, T, "R"), (self.lr[l], T, "W")])
         c.store_release(q)
-        return self.r[l]
+        return self.lr[l]
 
     def _smooth(self, l, sweeps):
         c, T, N = self.ctx, self.tile[l], self.none
         for _ in range(sweeps):
             r = self._residual(l)
-            c.submit("axpy", [1], [(self.w[l], N, "R"), (r, T, "R"), (self.x[l], T, "RW")], (1.0,))
+            c.submit("axpy", [1], [(self.w[l], N, "R"), (r, T, "R"), (self.lx[l], T, "RW")], (1.0,))
 
     def _cycle(self, l):
-        c = self.ctx
+        c, T = self.ctx, self.tile[l]
+        c.submit("fill", [1], [(self.lx[l], T, "W")], (0.0,))
         if l == len(self.levels) - 1:
             self._smooth(l, self.nu_c)
             return
         _, _, R, P = self.levels[l]
-        T = self.tile[l]
         self._smooth(l, self.nu1)
         r = self._residual(l)
-        self._spmv(R, r, self.b[l + 1], l + 1)
-        c.submit("fill", [1], [(self.x[l + 1], self.tile[l + 1], "W")], (0.0,))
+        self._spmv(R, r, self.lb[l + 1], l + 1)
         self._cycle(l + 1)
         e = c.store_create([self.sizes[l]], "f64")
-        self._spmv(P, self.x[l + 1], e, l)
-        c.submit("add", [1], [(self.x[l], T, "R"), (e, T, "R"), (self.x[l], T, "W")])
+        self._spmv(P, self.lx[l + 1], e, l)
+        c.submit("add", [1], [(self.lx[l], T, "R"), (e, T, "R"), (self.lx[l], T, "W")])
         c.store_release(e)
         self._smooth(l, self.nu2)
 
-    def cycle(self):
-        c, T, N = self.ctx, self.tile[0], self.none
+    def iteration(self):
+        c, T, N, d = self.ctx, self.tile[0], self.none, [1]
+        x, r, z, p, q = self.x, self.r, self.z, self.p, self.q
+        A = self.levels[0][0]
+        c.submit("spmv_csr", d, [(A[0], N, "R"), (A[1], N, "R"), (A[2], N, "R"),
+                                 (p, self.img[A[1]], "R"), (q, T, "W")])
+        c.submit("dot", d, [(p, T, "R"), (q, T, "R"), (self.pq, N, "Rd")], (1,))
+        c.submit("div", [], [(self.rho, N, "R"), (self.pq, N, "R"), (self.alpha, N, "W")])
+        c.submit("axpy", d, [(self.alpha, N, "R"), (p, T, "R"), (x, T, "RW")], (1.0,))
+        c.submit("axpy", d, [(self.alpha, N, "R"), (q, T, "R"), (r, T, "RW")], (-1.0,))
+        c.submit("dot", d, [(r, T, "R"), (r, T, "R"), (self.rr, N, "Rd")], (1,))
         self._cycle(0)
-        r = self._residual(0)
-        c.submit("dot", [1], [(r, T, "R"), (r, T, "R"), (self.rr, N, "Rd")], (1,))
+        c.submit("dot", d, [(r, T, "R"), (z, T, "R"), (self.rho_new, N, "Rd")], (1,))
+        c.submit("div", [], [(self.rho_new, N, "R"), (self.rho, N, "R"), (self.beta, N, "W")])
+        c.submit("copy", [], [(self.rho_new, N, "R"), (self.rho, N, "W")])
+        c.submit("mul", d, [(p, T, "R"), (self.beta, N, "R"), (p, T, "W")])
+        c.submit("add", d, [(p, T, "R"), (z, T, "R"), (p, T, "W")])

@@ -1159,9 +1159,11 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     for (int cs : {p.spmv_rowptr, p.spmv_col, p.spmv_val, p.spmv_x})
       if ((rc = ensure_alloc(c, S(cs)))) return rc;
   if ((rc = ensure_workspace(c, p))) return rc;
-  c.stats.launches += 1;
+  // the pass, plus the block-sum kernel when it reduces
+  const int n_launch = p.red_cstore.empty() ? 1 : 2;
+  c.stats.launches += n_launch;
   c.stats.alg_bytes += p.alg_bytes;
-  if (c.capturing) { c.capture_launches += 1; c.capture_bytes += p.alg_bytes; }
+  if (c.capturing) { c.capture_launches += n_launch; c.capture_bytes += p.alg_bytes; }
   if (c.analysis_only) return DFX_OK;
 
   // Launch-shape tuner.  A memoised pass runs once untimed (warm-up), then

@@ -223,6 +223,11 @@ static int run_phase(Server& S, int phase, int64_t n_items, int64_t off) {
 static void scheduler(Server* Sp) {
   Server& S = *Sp;
   (void)hipSetDevice(S.device);
+  // Requests admitted this round.  Their host arrays (the caller's CSR
+  // arrays, the request's copy of b) are sources of copies still in flight
+  // on the stream, so each is kept, and reported QUEUED, until the round's
+  // synchronisation; only then does its status become RUNNING.
+  std::vector<ServeReq> staged;
   for (;;) {
     // ---- admission -------------------------------------------------------------
     bool any_active = false;
@@ -236,11 +241,10 @@ static void scheduler(Server* Sp) {
         if (slot < 0 || S.used + q.footprint > S.cfg.hbm_budget) break;
         if (!admit_one(S, q, slot)) { fail_locked(S, "admission failed (device memory)"); break; }
         S.used += q.footprint;
-        ServeResult& res = S.results[q.ticket];
-        res.status = DFX_SOLVE_RUNNING;
-        res.t_admit = wall_now();
+        S.results[q.ticket].t_admit = wall_now();
         S.stats.admitted += 1;
         S.stats.peak_bytes = std::max<uint64_t>(S.stats.peak_bytes, S.used);
+        staged.push_back(std::move(q));
         S.queue.pop_front();
       }
       for (auto& sl : S.slots) any_active = any_active || sl.used;
@@ -287,6 +291,12 @@ static void scheduler(Server* Sp) {
     if (!e) e = hipMemcpyAsync(S.h_solves, S.d_solves, sizeof(SolveDev) * S.slots.size(), hipMemcpyDeviceToHost, S.stream);
     if (!e) e = hipStreamSynchronize(S.stream);
     if (e) { std::lock_guard<std::mutex> lk(S.mu); fail_locked(S, "round failed: " + std::string(hipGetErrorString((hipError_t)e))); break; }
+    {
+      // the admission copies have completed: the host arrays are free again
+      std::lock_guard<std::mutex> lk(S.mu);
+      for (const ServeReq& q : staged) S.results[q.ticket].status = DFX_SOLVE_RUNNING;
+    }
+    staged.clear();
     S.stats.rounds += 1;
     S.stats.row_updates += (int64_t)ipr * n_all * (int64_t)(RED_TH * 128);
     // ---- retire finished solves ---------------------------------------------------

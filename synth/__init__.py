@@ -140,58 +140,71 @@ def poisson_csr(m: int, dim: int):
 
 
 
-def restriction_csr(mc: int):
-    """Full weighting from the (2 mc + 1)^2 interior grid to the mc^2 one
-    (x fastest, Dirichlet boundary): coarse point (I, J) sits on fine point
-    (2I+1, 2J+1) with weight 1/4, its 4 edge neighbours 1/8 and 4 corners
-    1/16 (all exact), columns ascending.  Shape mc^2 x (2 mc + 1)^2."""
+def injection_csr(mc: int):
+    """Injection from the (2 mc + 1)^2 interior grid to the mc^2 one (x
+    fastest, Dirichlet boundary): coarse point (I, J) takes the value of fine
+    point (2I+1, 2J+1).  Shape mc^2 x (2 mc + 1)^2, one entry of 1 per row."""
     mf = 2 * mc + 1
     J, I = np.divmod(np.arange(mc * mc, dtype=np.int64), mc)
-    cols, vals = [], []
-    for dj in (-1, 0, 1):          # ascending fine row, then column: ascending index
-        for di in (-1, 0, 1):
-            cols.append((2 * J + 1 + dj) * mf + 2 * I + 1 + di)
-            vals.append(np.full(mc * mc, (2 - abs(di)) * (2 - abs(dj)) / 16.0))
-    col = np.stack(cols, axis=1).ravel().astype(np.int32)
-    val = np.stack(vals, axis=1).ravel()
-    rowptr = (np.arange(mc * mc + 1, dtype=np.int64) * 9).astype(np.int32)
-    return rowptr, col, val
+    col = ((2 * J + 1) * mf + 2 * I + 1).astype(np.int32)
+    rowptr = np.arange(mc * mc + 1, dtype=np.int32)
+    return rowptr, col, np.ones(mc * mc)
 
 
-def prolongation_csr(mc: int):
-    """Bilinear interpolation from the mc^2 grid to the (2 mc + 1)^2 one:
-    4 times the transpose of restriction_csr (weights 1, 1/2, 1/4), columns
-    ascending."""
-    rp, col, val = restriction_csr(mc)
+def bilinear_csr(mc: int):
+    """Bilinear interpolation from the mc^2 grid to the (2 mc + 1)^2 one,
+    zero outside the grid: a fine point on a coarse point takes its value
+    (weight 1), one between two coarse points along a line their mean
+    (1/2 each), one at a cell centre the mean of the four corners (1/4 each).
+    Columns ascending."""
     mf = 2 * mc + 1
-    rows = np.repeat(np.arange(mc * mc, dtype=np.int64), 9)
-    order = np.lexsort((rows, col.astype(np.int64)))    # by fine row, then coarse column
-    fr, cc, vv = col[order].astype(np.int64), rows[order], 4.0 * val[order]
+    j, i = np.divmod(np.arange(mf * mf, dtype=np.int64), mf)
+
+    def axis(k):
+        # coarse neighbours along one axis and their weights: odd fine index
+        # 2K+1 sits on coarse K; even 2K lies between coarse K-1 and K
+        odd = (k % 2) == 1
+        lo = np.where(odd, (k - 1) // 2, k // 2 - 1)
+        hi = np.where(odd, -1, k // 2)
+        wl = np.where(odd, 1.0, 0.5)
+        wh = np.where(odd, 0.0, 0.5)
+        return (lo, wl), (hi, wh)
+
+    cols, vals = [], []
+    for (cj, wj) in axis(j):            # ascending coarse row J first,
+        for (ci, wi) in axis(i):        # then coarse column I: ascending index
+            ok = (cj >= 0) & (cj < mc) & (ci >= 0) & (ci < mc) & (wj > 0) & (wi > 0)
+            cols.append(np.where(ok, cj * mc + ci, -1))
+            vals.append(np.where(ok, wj * wi, 0.0))
+    col = np.stack(cols, axis=1)
+    val = np.stack(vals, axis=1)
+    keep = col >= 0
     rowptr = np.zeros(mf * mf + 1, dtype=np.int64)
-    np.cumsum(np.bincount(fr, minlength=mf * mf), out=rowptr[1:])
-    return rowptr.astype(np.int32), cc.astype(np.int32), vv
+    np.cumsum(keep.sum(axis=1), out=rowptr[1:])
+    return rowptr.astype(np.int32), col[keep].astype(np.int32), val[keep]
 
 
-def gmg_levels(m0: int, nlev: int, omega: float = 0.8):
+def gmg_levels(m0: int, nlev: int):
     """The multigrid hierarchy of the m0^2 Poisson problem (m0 = 2^k - 1):
     level l has side m_l = (m_{l-1} - 1) / 2 and operator poisson_csr(m_l)
     scaled by 4^-l (the 5-point operator rediscretised on the coarser grid,
-    in units of the finest h^2; every value stays exact), smoothing weight
-    omega / (4 4^-l), and the transfers to and from level l+1.  Returns
-    [(A, w, R, P)] with R = P = None on the coarsest level."""
+    in units of the finest h^2; every value stays exact), whose diagonal is
+    4 * 4^-l, and the transfers to and from level l+1 (injection and
+    bilinear interpolation).  Returns [(A, diag, R, P)] with R = P = None on
+    the coarsest level."""
     out, m = [], m0
     for l in range(nlev):
         rp, col, val = poisson_csr(m, 2)
         A = (rp, col, val * 0.25 ** l)
-        w = omega / (4.0 * 0.25 ** l)
+        diag = 4.0 * 0.25 ** l
         if l < nlev - 1:
             if m % 2 == 0 or m < 3:
                 raise ValueError("side must be 2^k - 1 on every level but the last")
             mc = (m - 1) // 2
-            out.append((A, w, restriction_csr(mc), prolongation_csr(mc)))
+            out.append((A, diag, injection_csr(mc), bilinear_csr(mc)))
             m = mc
         else:
-            out.append((A, w, None, None))
+            out.append((A, diag, None, None))
     return out
 
 

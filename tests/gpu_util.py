@@ -42,9 +42,14 @@ def rel_err(g, o):
 def bs_run(c, n, dtype="f64", passes=1, points=1):
     npdt = np.float64 if dtype == "f64" else np.float32
     S, K, T = synth.bs_inputs(n, npdt)
+    # the oracle's own scalars; the device forms rv = r + sigma^2/2 itself
     r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL, npdt)
     hS, hK, hT = upload(c, S), upload(c, K), upload(c, T)
-    hr, hs, hv = (upload(c, np.array(v, dtype=npdt)) for v in (r, sig, rv))
+    hr, hs = (upload(c, np.array(v, dtype=npdt)) for v in (synth.BS_RATE, synth.BS_VOL))
+    hv = dfx.apps.bs_drift(c, hr, hs, dtype)
+    got_rv = float(c.store_read(hv, [], dtype))
+    assert got_rv == rv, (got_rv, rv)
+    c.stats_reset()
     out = None
     for _ in range(passes):
         if out:

@@ -1,6 +1,7 @@
 """Automatic window sizing on the GPU: the windows it settles on give the
 same groups, hence the same bits, as a fixed window large enough for every
-fusion (Black-Scholes from a window of 2, CG from 1)."""
+fusion (Black-Scholes from a window of 2, CG from 1), and the results agree
+with the oracle."""
 import numpy as np
 import pytest
 
@@ -16,13 +17,15 @@ def test_auto_window_black_scholes_bit_identical():
     n = 3 * 4096 + 77
     note("auto window: black-scholes n=%d" % n)
     c = dfx.Context(device=0, window_size=2, auto_window=64)
-    _, call_a, put_a = bs_run(c, n, passes=2)
+    (S, K, T, r, sig, rv), call_a, put_a = bs_run(c, n, passes=2)
     assert [g["prefix_len"] for g in c.groups()] == [28, 28] and c.window_size() == 32
     c.close()
     c = dfx.Context(device=0, window_size=64)
     _, call_f, put_f = bs_run(c, n, passes=2)
     c.close()
     assert np.array_equal(call_a, call_f) and np.array_equal(put_a, put_f)
+    oc, op = wl.black_scholes(S, K, T, r, sig, rv)
+    assert rel_err_floor(call_a, oc) <= 1e-12 and rel_err_floor(put_a, op) <= 1e-12
 
 
 def test_auto_window_cg_bit_identical():
@@ -42,6 +45,10 @@ def test_auto_window_cg_bit_identical():
         c.close()
     (ra, xa, ga), (rf, xf, gf) = out
     assert ga == gf and ra == rf and np.array_equal(xa, xf)
+    xo, ho = wl.cg(rowptr, col, val, b, 20)
+    assert rel_err_floor(xa, xo) <= 1e-12
+    for g, o in zip(ra, ho[1:]):
+        assert abs(g - o) <= 1e-10 * o
 
 
 def test_window_16_black_scholes_split_bit_identical():

@@ -92,3 +92,44 @@ def test_cg256_full_size_graph():
     for k, (gv, o) in enumerate(zip(rho, ho)):
         assert abs(gv - o) <= TOL_RED * abs(o), k
     assert rel_err_floor(x, xo) <= TOL_ELEM_F64
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as fh:
+        return [float(line) for line in fh if not line.startswith("#")]
+
+
+def test_cg256_rho_history_500_iterations():
+    """The residual history rho_k = r_k.r_k of 500 CG iterations on the
+    256^3 system, as the bench runs them (one eager iteration, then one
+    iteration recorded as a graph and replayed), against the oracle's
+    history stored in tests/golden/cg256_rho.txt (written by
+    tests/golden/make_cg256_rho.py, which calls only the oracle)."""
+    m, dim, n, iters = 256, 3, 256 ** 3, 500
+    ho = _golden("cg256_rho.txt")
+    assert len(ho) == iters + 1
+    note("cg 256^3: %d iterations against the stored oracle history" % iters)
+    rowptr, col, val = synth.poisson_csr(m, dim)
+    b = synth.rhs(n, synth.CG256_SEED)
+    c = ctx(window=16)
+    hs = [upload(c, a) for a in (rowptr, col, val, b)]
+    del rowptr, col, val
+    cg = dfx.apps.CG(c, *hs, n)
+    rho = [float(c.store_read(cg.rho, [], "f64"))]
+    cg.iteration()
+    rho.append(float(c.store_read(cg.rho, [], "f64")))
+    c.graph_begin()
+    cg.iteration()
+    g = c.graph_end()
+    for k in range(iters - 1):
+        c.graph_launch(g)
+        rho.append(float(c.store_read(cg.rho, [], "f64")))
+        if k % 100 == 99:
+            note("cg 256^3: %d iterations" % (k + 2))
+    c.close()
+    worst = max(abs(gv - o) / o for gv, o in zip(rho, ho))
+    note("cg 256^3: worst relative difference of rho over %d iterations %.2e" % (iters, worst))
+    for k, (gv, o) in enumerate(zip(rho, ho)):
+        assert abs(gv - o) <= TOL_RED * abs(o), (k, gv, o)

@@ -1,21 +1,29 @@
 """Plans loaded from the on-disk cache execute with no analysis and give the
 same bits as the plans the saving context built (Black-Scholes, CG,
-BiCGSTAB)."""
+BiCGSTAB), and those results agree with the oracle."""
 import numpy as np
 import pytest
 
 import paper_2406_18109_amd as dfx
 import synth
-from gpu_util import bs_run, note, upload
+from gpu_util import bs_run, note, rel_err_floor, upload
+from oracle import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
 
+M_CD = 48
+
+
+def _systems():
+    rowptr, col, val = synth.convdiff_csr(M_CD, 2)
+    return (rowptr, col, val), synth.rhs(M_CD * M_CD, 4130)
+
+
 def _run(c):
     _, call, put = bs_run(c, 3 * 4096 + 77, passes=2)
-    m = 48
-    rowptr, col, val = synth.convdiff_csr(m, 2)
-    b = synth.rhs(m * m, 4130)
+    m = M_CD
+    (rowptr, col, val), b = _systems()
     hs = [upload(c, a) for a in (rowptr, col, val, b)]
     res = [call, put]
     for cls in (dfx.apps.CG, dfx.apps.BiCGSTAB):
@@ -24,6 +32,18 @@ def _run(c):
             s.iteration()
         res.append(c.store_read(s.x, [m * m], "f64"))
     return res
+
+
+def _check_oracle(res):
+    call, put, x_cg, x_bi = res
+    n = 3 * 4096 + 77
+    S, K, T = synth.bs_inputs(n)
+    oc, op = wl.black_scholes(S, K, T, *wl.bs_scalars(synth.BS_RATE, synth.BS_VOL))
+    assert rel_err_floor(call, oc) <= 1e-12 and rel_err_floor(put, op) <= 1e-12
+    (rowptr, col, val), b = _systems()
+    # CG on the nonsymmetric matrix is still a well-defined stream of tasks
+    assert rel_err_floor(x_cg, wl.cg(rowptr, col, val, b, 5)[0]) <= 1e-12
+    assert rel_err_floor(x_bi, wl.bicgstab(rowptr, col, val, b, 5)[0]) <= 1e-12
 
 
 def test_loaded_plans_bit_identical(tmp_path):
@@ -42,6 +62,7 @@ def test_loaded_plans_bit_identical(tmp_path):
     assert st["memo_misses"] == 0
     for x, y in zip(ra, rb):
         assert np.array_equal(x, y)
+    _check_oracle(rb)
 
 
 def test_capture_from_loaded_plans_without_eager_run(tmp_path):
@@ -86,3 +107,7 @@ def test_capture_from_loaded_plans_without_eager_run(tmp_path):
     c.close()
     assert st["memo_misses"] == 0
     assert rho_c == rho_a and np.array_equal(x_c, x_a)
+    xo, ho = wl.cg(rowptr, col, val, b, 3)
+    assert rel_err_floor(x_c, xo) <= 1e-12
+    for g, o in zip(rho_c, ho):
+        assert abs(g - o) <= 1e-10 * o

@@ -78,6 +78,58 @@ def test_alone_equals_mix_and_matches_oracle():
     c.close()
 
 
+def test_multi_tile_alone_equals_mix_and_matches_oracle():
+    """Solves of several tiles (one tile holds 4096 unknowns): sides 129, 300
+    and 512 (5, 22 and 64 tiles) alone, then inside a mix of 16 uneven solves
+    that also holds one-tile ones.  Each multi-tile result is bit-identical
+    alone and in the mix, bit-identical to the task-stream CG run for the
+    same number of iterations, and within tolerance of the oracle's CG."""
+    big = [129, 300, 512]
+    mix = [129, 40, 300, 64, 512, 23, 96, 200, 33, 257, 50, 150, 8, 380, 70, 450]
+    mats = {s: synth.poisson_csr(s, 2) for s in set(mix)}
+    rhs = {s: synth.serve_rhs(600 + s, s * s) for s in set(mix)}
+    alone = {}
+    for s in big:
+        c = ctx()
+        c.serve_start(hbm_budget=1 << 30, max_slots=4, tol=TOL, max_iter=20 * s)
+        note("serve alone side=%d" % s)
+        t = c.serve_submit(*mats[s], rhs[s])
+        r = c.serve_wait(t, 300)
+        assert r["status"] == B.SOLVE_CONVERGED, (s, r)
+        alone[s] = (r, c.serve_read_x(t, s * s))
+        c.serve_stop()
+        c.close()
+    c = ctx()
+    c.serve_start(hbm_budget=1 << 30, max_slots=8, tol=TOL, max_iter=20 * max(mix))
+    note("serve mix of %d solves" % len(mix))
+    tickets = []
+    for i, s in enumerate(mix):
+        tickets.append((c.serve_submit(*mats[s], rhs[s]), s))
+        time.sleep(0.003 * (i % 4))
+    inmix = {}
+    for t, s in tickets:
+        r = c.serve_wait(t, 600)
+        assert r["status"] == B.SOLVE_CONVERGED, (s, r)
+        x = c.serve_read_x(t, s * s)
+        rp, col, val = mats[s]
+        true_res = np.linalg.norm(rhs[s] - cnum.spmv(rp, col, val, x)) / np.linalg.norm(rhs[s])
+        assert r["rel_residual"] <= TOL and true_res <= 2 * TOL, (s, r, true_res)
+        inmix[s] = (r, x)
+    c.serve_stop()
+    c.close()
+    for s in big:
+        (ra, xa), (rm, xm) = alone[s], inmix[s]
+        assert ra["iterations"] == rm["iterations"] and ra["rel_residual"] == rm["rel_residual"], s
+        assert np.array_equal(xa, xm), s
+        note("serve side=%d: task-stream CG, %d iterations" % (s, ra["iterations"]))
+        assert np.array_equal(xa, _task_stream_cg(*mats[s], rhs[s], ra["iterations"])), s
+        note("serve side=%d: oracle CG" % s)
+        xo, ho = wl.cg(*mats[s], rhs[s], ra["iterations"])
+        assert rel_err_floor(xa, xo) <= 1e-9, s
+        ro = math.sqrt(ho[-1] / ho[0])
+        assert abs(ra["rel_residual"] - ro) <= 1e-9 * ro, s
+
+
 def test_iterations_per_round_do_not_change_results():
     """A solve that converges inside a multi-iteration round stops on the
     device: x, the iteration count and the residual are those of one
