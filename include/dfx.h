@@ -217,6 +217,28 @@ int dfx_flush(dfx_ctx* ctx);
 /* Flush and wait for all dispatched work. */
 int dfx_sync(dfx_ctx* ctx);
 
+/* Allocation-free flush, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same analysis and dispatch as dfx_flush, but:
+ *   - the block sums of every reduction go to a fixed array in the library's
+ *     device memory (one per device, set up by dfx_create, kept until the
+ *     process ends), not to the plan's workspace: at most 16384 blocks per
+ *     pass with a reduction (a pass over about 2^26 FP64 elements uses
+ *     4096); a larger pass gives DFX_EUNSUPPORTED;
+ *   - a group that would need device memory (a store's first allocation,
+ *     e.g. the output of a task never run before) is not launched:
+ *     DFX_ESTATE, and that group and the rest stay in the window (groups
+ *     dispatched before it stay dispatched);
+ *   - device frees that retiring stores would make are deferred to the next
+ *     dfx_flush, dfx_submit that dispatches, or dfx_destroy.
+ * No hipMalloc, hipFree or allocation callback is called.  Host-side
+ * analysis of a window not seen before still uses the C++ heap.  Every
+ * context on one device shares the array and each call overwrites it:
+ * allocation-free flushes that overlap on one device (different streams or
+ * threads) race.  Nothing in the array needs clearing: every block sum is
+ * written before it is read. */
+int dfx_flush_noalloc(dfx_ctx* ctx);
+
 /* ---- whole-region graphs ----------------------------------------------- */
 /* Flush, then record every launch dispatched until dfx_graph_end into one
  * hipGraph.  No store may need new memory while recording (DFX_ESTATE). */

@@ -115,6 +115,7 @@ SIGNATURES = {
     "dfx_part_image": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_int32)]),
     "dfx_submit": (C.c_int, [C.c_void_p, C.POINTER(dfx_task)]),
     "dfx_flush": (C.c_int, [C.c_void_p]),
+    "dfx_flush_noalloc": (C.c_int, [C.c_void_p]),
     "dfx_sync": (C.c_int, [C.c_void_p]),
     "dfx_graph_begin": (C.c_int, [C.c_void_p]),
     "dfx_graph_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
@@ -330,6 +331,9 @@ class Context:
 
     def flush(self):
         self._chk(self.L.dfx_flush(self.h))
+
+    def flush_noalloc(self):
+        self._chk(self.L.dfx_flush_noalloc(self.h))
 
     def sync(self):
         self._chk(self.L.dfx_sync(self.h))

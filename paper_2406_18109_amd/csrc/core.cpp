@@ -94,6 +94,10 @@ static void* dev_alloc(Ctx& c, size_t bytes) {
 
 static void dev_free(Ctx& c, void* p, size_t bytes) {
   if (!p) return;
+  if (c.no_alloc) {   // returned at the next call that may free
+    c.deferred_free.emplace_back(p, bytes);
+    return;
+  }
   if (c.cfg.dealloc) {
     c.cfg.dealloc(p, bytes, (void*)c.stream, c.cfg.alloc_user);
     return;
@@ -101,9 +105,19 @@ static void dev_free(Ctx& c, void* p, size_t bytes) {
   (void)hipFreeAsync(p, c.stream);
 }
 
+static void drain_deferred_frees(Ctx& c) {
+  if (c.no_alloc) return;
+  std::vector<std::pair<void*, size_t>> v;
+  v.swap(c.deferred_free);
+  for (auto& pb : v) dev_free(c, pb.first, pb.second);
+}
+
 static int ensure_alloc(Ctx& c, StoreRec& s) {
   if (s.ptr || s.bytes == 0) return DFX_OK;
   if (c.analysis_only) return DFX_OK;
+  if (c.no_alloc)
+    return fail(c, DFX_ESTATE, "store " + std::to_string(s.id) +
+                                   " needs device memory in an allocation-free flush");
   if (c.capturing)
     return fail(c, DFX_ESTATE, "store " + std::to_string(s.id) +
                                    " needs memory while a graph is being recorded");
@@ -1158,7 +1172,15 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   if (p.kind == 1)
     for (int cs : {p.spmv_rowptr, p.spmv_col, p.spmv_val, p.spmv_x})
       if ((rc = ensure_alloc(c, S(cs)))) return rc;
-  if ((rc = ensure_workspace(c, p))) return rc;
+  if (c.no_alloc && !c.analysis_only) {
+    if (!p.red_cstore.empty() && p.grid > NOALLOC_BLOCKS)
+      return fail(c, DFX_EUNSUPPORTED, "pass of " + std::to_string(p.grid) +
+                                           " blocks exceeds the allocation-free scratch (" +
+                                           std::to_string(NOALLOC_BLOCKS) + " blocks)");
+    if (!c.scratch) return fail(c, DFX_ESTATE, "no scratch memory on this device");
+  } else if (!c.no_alloc && (rc = ensure_workspace(c, p))) {
+    return rc;
+  }
   // the pass, plus the block-sum kernel when it reduces
   const int n_launch = p.red_cstore.empty() ? 1 : 2;
   c.stats.launches += n_launch;
@@ -1172,7 +1194,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   // own.  A candidate replaces the default only if its faster run beats the
   // default's by 3 %.  A graph being recorded takes the default shape.
   bool timed = false;
-  if (!p.tune_cand.empty()) {
+  if (!p.tune_cand.empty() && !c.no_alloc) {
     const int nc = (int)p.tune_cand.size();
     if (p.tune_pending >= 0 && !c.capturing) {
       float ms = 0.f;
@@ -1257,7 +1279,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   F.n_red = P.n_red;
   F.nblocks = (int32_t)((p.n_tiles + 4 * p.tiles_per_wave - 1) / (4 * p.tiles_per_wave));
   for (int k = 0; k < P.n_red; ++k) {
-    P.red_partials[k] = (char*)p.ws + part * k;
+    P.red_partials[k] = c.no_alloc ? (char*)c.scratch + (size_t)NOALLOC_BLOCKS * 8 * k : (char*)p.ws + part * k;
     F.partials[k] = P.red_partials[k];
     F.result[k] = S(p.red_cstore[k]).ptr;
     F.init[k] = p.red_init[k];
@@ -1293,6 +1315,7 @@ static double now_s() {
 // size doubled instead
 static int dispatch_one(Ctx& c, bool may_grow = false) {
   if (c.window.empty()) return DFX_OK;
+  if (!c.deferred_free.empty()) drain_deferred_frees(c);
   std::vector<int64_t> order;
   std::string key = canonical_key(c, order);
   Plan* plan = nullptr;
@@ -1349,6 +1372,27 @@ static int dispatch_one(Ctx& c, bool may_grow = false) {
   if (grow && hit && plan->prefix == (int)c.window.size()) {
     c.window_cur = (int)std::min<int64_t>(2 * (int64_t)c.window_cur, c.cfg.auto_window);
     return DFX_OK;
+  }
+  if (c.no_alloc && !c.analysis_only) {
+    // nothing of the group is launched unless every pass can run without
+    // device memory: its stores allocated, its block sums within the scratch
+    for (auto& p : plan->passes) {
+      std::vector<int> need;
+      for (auto& s : p.ins) need.push_back(s.cstore);
+      for (auto& s : p.outs) need.push_back(s.cstore);
+      for (int cs : p.bc_cstore) need.push_back(cs);
+      for (int cs : p.red_cstore) need.push_back(cs);
+      if (p.kind == 1) for (int cs : {p.spmv_rowptr, p.spmv_col, p.spmv_val, p.spmv_x}) need.push_back(cs);
+      for (int cs : need) {
+        const StoreRec& s = c.stores.at(order[cs]);
+        if (!s.ptr && s.bytes != 0)
+          return fail(c, DFX_ESTATE, "store " + std::to_string(s.id) +
+                                         " needs device memory in an allocation-free flush");
+      }
+      if (!p.red_cstore.empty() && p.grid > NOALLOC_BLOCKS)
+        return fail(c, DFX_EUNSUPPORTED, "pass of " + std::to_string(p.grid) +
+                                             " blocks exceeds the allocation-free scratch");
+    }
   }
   for (auto& p : plan->passes) {
     int rc = run_pass(c, p, order);
@@ -1490,6 +1534,8 @@ int dfx_create(const dfx_config* cfg, dfx_ctx** out) {
       if (hipMalloc(&g_dummy_stream, 4096) != hipSuccess) { delete c; return DFX_ENOMEM; }
       if (hipMemset(g_dummy_stream, 0, 4096) != hipSuccess) { delete c; return DFX_EHIP; }
     }
+    // the allocation-free flush's scratch array on this device (current)
+    if (scratch_address(cfg->device, &c->scratch) != 0) { delete c; return DFX_EHIP; }
     if (!cfg->alloc) {
       hipMemPool_t pool;
       if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
@@ -1507,6 +1553,7 @@ int dfx_destroy(dfx_ctx* c) {
   if (c->server) (void)dfx_serve_stop(c);
   int rc = c->capturing ? DFX_OK : flush(*c);
   if (!c->analysis_only) {
+    drain_deferred_frees(*c);
     for (auto& kv : c->memo) release_plan(*c, *kv.second);
     for (auto& kv : c->stores)
       if (kv.second.ptr && !kv.second.external) dev_free(*c, kv.second.ptr, kv.second.bytes);
@@ -1697,6 +1744,14 @@ int dfx_submit(dfx_ctx* c, const dfx_task* task) {
 }
 
 int dfx_flush(dfx_ctx* c) { return c ? flush(*c) : DFX_EINVAL; }
+
+int dfx_flush_noalloc(dfx_ctx* c) {
+  if (!c) return DFX_EINVAL;
+  c->no_alloc = true;
+  const int rc = flush(*c);
+  c->no_alloc = false;
+  return rc;
+}
 
 // ---- on-disk plan cache ----------------------------------------------------
 // File: magic, format version, build stamp, FNV-1a 64 checksum of the body,

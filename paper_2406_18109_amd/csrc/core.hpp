@@ -18,6 +18,7 @@ int launch_vm(const VmParams& P, int is_f64, int tier, int rows, hipStream_t str
 int arith_waves_per_cu(int is_f64, int n_in, int rows);
 int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream);
 int stream_bucket(int n_in, int tier);
+int scratch_address(int device, void** out);
 
 enum PartKind { PK_NONE = 0, PK_TILING = 1, PK_IMAGE = 2 };
 
@@ -160,6 +161,11 @@ struct Ctx {
 
   dfx_stats stats{};
   void* server = nullptr;   // continuous-batching CG server, if started
+  // allocation-free flush: the device's scratch array, the mode flag, and the
+  // device frees deferred while the mode is on
+  void* scratch = nullptr;
+  bool no_alloc = false;
+  std::vector<std::pair<void*, size_t>> deferred_free;
   // resident waves of the arithmetic kernels: [f64][stream bucket 2/4/6][rows 1]
   int n_cu = 0;
   int waves_cu[2][3][2] = {};

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "dev_common.h"
 #include "vm.h"
 
@@ -57,6 +59,32 @@ int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream) {
   if (is_f64) hipLaunchKernelGGL(vm_final<double>, dim3(1), dim3(FINAL_BLOCK), 0, stream, F);
   else hipLaunchKernelGGL(vm_final<float>, dim3(1), dim3(FINAL_BLOCK), 0, stream, F);
   return (int)hipGetLastError();
+}
+
+// Scratch memory of the allocation-free flush: for each of the VM_MAXRED
+// reduction slots, room for NOALLOC_BLOCKS block sums of up to 8 bytes.
+// Every device the library runs on holds its own copy until the process
+// ends.  Host code never uses the array's name: it takes the device address
+// from scratch_address, once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// The device address of `scratch` on `device`, which must be the current
+// device.  Looked up once per device and kept; returns a hipError_t.
+int scratch_address(int device, void** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  if (device < 0 || device >= kMaxDev || !out) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return 0;
 }
 
 int stream_bucket(int n_in, int tier) { return tier == TIER_POW ? VM_MAXIN : n_in <= 2 ? 2 : n_in <= 4 ? 4 : 6; }

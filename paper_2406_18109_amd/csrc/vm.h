@@ -128,6 +128,12 @@ struct VmParams {
   VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
 
+// Allocation-free execution (dfx_flush_noalloc): the block sums of a pass's
+// reductions go to a fixed device array of NOALLOC_BLOCKS sums per reduction
+// slot instead of the plan's workspace.
+constexpr int NOALLOC_BLOCKS = 16384;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)NOALLOC_BLOCKS * VM_MAXRED * 8;
+
 // The block-sum kernel: reduces `nblocks` block sums per reduction and stores
 // (init) or accumulates into the 0-d result.
 struct VmFinal {
