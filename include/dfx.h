@@ -275,6 +275,52 @@ int dfx_group_count(dfx_ctx* ctx, int64_t* n);
 int dfx_group_get(dfx_ctx* ctx, int64_t i, dfx_group_info* out);
 
 
+/* ---- batched persistent execution of independent task streams ---------- */
+/* Not in the paper (the executor's batching): many independent task streams
+ * of uneven sizes run in one persistent launch.  A stream is what one
+ * context dispatches between dfx_batch_record_begin and dfx_batch_record_end:
+ * its windows are analysed, fused and lowered as usual (section 4's fused
+ * tasks, section 5's temporaries and memoisation), but the passes are kept in
+ * the batch instead of launched.  Passes recorded before dfx_batch_loop_begin
+ * run once; those after it form a body repeated up to max_iter times, which
+ * stops early once *conv_a <= tol * *conv_b (two 0-d FP64 stores of the
+ * context, compared in FP64 after each repetition; conv_a = conv_b = 0: no
+ * test).  dfx_batch_run launches one persistent kernel over every stream:
+ * waves claim (stream, pass, tile run) work items from per-stream claim
+ * counters, and the wave that completes a pass's last run reduces its tile
+ * sums with the same canonical tree as the ordinary path and advances the
+ * stream; no wave waits on another.  Every result is therefore bit-identical
+ * to the same stream run through dfx_flush.
+ * Limits: FP64 passes of at most 8 live values and 6 input streams (tiers
+ * with more registers or pow give DFX_EUNSUPPORTED at record_end) and at most
+ * 4096 x 64 tiles per pass.  Streams of one batch run concurrently: no
+ * stream may write memory another stream reads or writes.  The stores a
+ * stream uses must stay alive (not released by every reference) until the
+ * batch is destroyed; the batch keeps device addresses, not references.
+ * Recording is exclusive: one context at a time (DFX_ESTATE otherwise).
+ * dfx_batch_run synchronises the device first (the recording contexts' work
+ * is complete before the launch), then launches asynchronously on the
+ * batch's stream.  restart != 0 starts every stream from its first pass;
+ * restart = 0 resumes streams paused by round_limit (> 0: a stream pauses
+ * after that many body repetitions in one launch) and leaves finished ones.
+ * dfx_batch_wait synchronises and reads the stream states back; it returns
+ * DFX_EHIP if the kernel's stall detector ended the launch (no pass of any
+ * stream completed for several seconds).  Errors: dfx_batch_last_error. */
+typedef struct dfx_batch dfx_batch;
+enum { DFX_BATCH_RUNNING = 0, DFX_BATCH_DONE = 1, DFX_BATCH_PAUSED = 2 };
+int dfx_batch_create(int32_t device, void* stream, dfx_batch** out);
+int dfx_batch_destroy(dfx_batch* b);
+const char* dfx_batch_last_error(dfx_batch* b);
+int dfx_batch_record_begin(dfx_batch* b, dfx_ctx* ctx);
+int dfx_batch_loop_begin(dfx_batch* b, dfx_ctx* ctx);
+int dfx_batch_record_end(dfx_batch* b, dfx_ctx* ctx, int32_t max_iter, dfx_store conv_a, dfx_store conv_b,
+                         double tol, int32_t* stream_id);
+int dfx_batch_run(dfx_batch* b, int32_t round_limit, int32_t restart);
+int dfx_batch_wait(dfx_batch* b);
+/* After dfx_batch_wait: body repetitions completed and DFX_BATCH_* status. */
+int dfx_batch_stream_info(dfx_batch* b, int32_t stream_id, int32_t* iterations, int32_t* status);
+int dfx_batch_counts(dfx_batch* b, int32_t* n_streams, int32_t* n_passes, int32_t* grid);
+
 /* ---- serving: continuous batching of independent CG solves -------------- */
 /* Not in the paper: a request loop over the same arithmetic.  A scheduler
  * thread admits queued solves while a slot is free and their HBM footprint

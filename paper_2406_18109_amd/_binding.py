@@ -136,6 +136,17 @@ SIGNATURES = {
     "dfx_serve_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "dfx_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(dfx_serve_counters)]),
     "dfx_serve_stop": (C.c_int, [C.c_void_p]),
+    "dfx_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dfx_batch_destroy": (C.c_int, [C.c_void_p]),
+    "dfx_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "dfx_batch_record_begin": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dfx_batch_loop_begin": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dfx_batch_record_end": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_double,
+                                       C.POINTER(C.c_int32)]),
+    "dfx_batch_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "dfx_batch_wait": (C.c_int, [C.c_void_p]),
+    "dfx_batch_stream_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dfx_batch_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
 }
 
 
@@ -445,3 +456,67 @@ class Context:
                         "temporaries": sorted(gi.temporaries[:gi.n_temporaries]),
                         "alg_bytes": gi.alg_bytes})
         return out
+
+
+class Batch:
+    """A batch of independent task streams run in one persistent launch
+    (dfx_batch_*): each stream is what one context dispatches between
+    record_begin and record_end."""
+
+    RUNNING, DONE, PAUSED = 0, 1, 2
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = lib()
+        self.torch_stream = None
+        if stream is None:
+            import torch
+            self.torch_stream = torch.cuda.Stream(device=device)
+            stream = self.torch_stream.cuda_stream
+        h = C.c_void_p()
+        rc = self.L.dfx_batch_create(device, C.c_void_p(int(stream)), C.byref(h))
+        if rc != 0:
+            raise DfxError(rc, "dfx_batch_create failed")
+        self.h = h
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise DfxError(rc, self.L.dfx_batch_last_error(self.h).decode())
+        return rc
+
+    def record_begin(self, ctx: Context):
+        self._chk(self.L.dfx_batch_record_begin(self.h, ctx.h))
+
+    def loop_begin(self, ctx: Context):
+        self._chk(self.L.dfx_batch_loop_begin(self.h, ctx.h))
+
+    def record_end(self, ctx: Context, max_iter: int = 0, conv_a: int = 0, conv_b: int = 0, tol: float = 0.0) -> int:
+        sid = C.c_int32()
+        self._chk(self.L.dfx_batch_record_end(self.h, ctx.h, max_iter, conv_a, conv_b, tol, C.byref(sid)))
+        return sid.value
+
+    def run(self, round_limit: int = 0, restart: bool = True):
+        self._chk(self.L.dfx_batch_run(self.h, round_limit, 1 if restart else 0))
+
+    def wait(self):
+        self._chk(self.L.dfx_batch_wait(self.h))
+
+    def stream_info(self, sid: int):
+        it, st = C.c_int32(), C.c_int32()
+        self._chk(self.L.dfx_batch_stream_info(self.h, sid, C.byref(it), C.byref(st)))
+        return it.value, st.value
+
+    def counts(self):
+        a, b, g = C.c_int32(), C.c_int32(), C.c_int32()
+        self._chk(self.L.dfx_batch_counts(self.h, C.byref(a), C.byref(b), C.byref(g)))
+        return {"streams": a.value, "passes": b.value, "grid": g.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dfx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

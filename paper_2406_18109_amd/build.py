@@ -31,12 +31,14 @@ DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
 SOURCES = [
     ("core.cpp", False),
     ("serve.cpp", False),
+    ("batch.cpp", False),
     ("kernels.hip", True),
     ("vm_tier0.hip", True),
     ("vm_tier1.hip", True),
     ("vm_tier2.hip", True),
     ("vm_tier3.hip", True),
     ("serve.hip", True),
+    ("batch.hip", True),
 ]
 
 

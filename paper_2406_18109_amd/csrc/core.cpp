@@ -1178,7 +1178,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
                                            " blocks exceeds the allocation-free scratch (" +
                                            std::to_string(NOALLOC_BLOCKS) + " blocks)");
     if (!c.scratch) return fail(c, DFX_ESTATE, "no scratch memory on this device");
-  } else if (!c.no_alloc && (rc = ensure_workspace(c, p))) {
+  } else if (!c.no_alloc && !c.batch_rec && (rc = ensure_workspace(c, p))) {
     return rc;
   }
   // the pass, plus the block-sum kernel when it reduces
@@ -1194,7 +1194,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   // own.  A candidate replaces the default only if its faster run beats the
   // default's by 3 %.  A graph being recorded takes the default shape.
   bool timed = false;
-  if (!p.tune_cand.empty() && !c.no_alloc) {
+  if (!p.tune_cand.empty() && !c.no_alloc && !c.batch_rec) {
     const int nc = (int)p.tune_cand.size();
     if (p.tune_pending >= 0 && !c.capturing) {
       float ms = 0.f;
@@ -1298,6 +1298,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.sp_stage = st && (st[0] == '0' || st[0] == '1') ? st[0] == '1' : p.n_tiles >= 256;
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
+  if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, pick_rows(c, p), c.stream);
   if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
@@ -1552,6 +1553,7 @@ int dfx_destroy(dfx_ctx* c) {
   if (!c) return DFX_EINVAL;
   if (c->server) (void)dfx_serve_stop(c);
   int rc = c->capturing ? DFX_OK : flush(*c);
+  if (c->batch_rec) batch_record_drop(*c);
   if (!c->analysis_only) {
     drain_deferred_frees(*c);
     for (auto& kv : c->memo) release_plan(*c, *kv.second);

@@ -19,6 +19,9 @@ int arith_waves_per_cu(int is_f64, int n_in, int rows);
 int launch_vm_final(const VmFinal& F, int is_f64, hipStream_t stream);
 int stream_bucket(int n_in, int tier);
 int scratch_address(int device, void** out);
+struct Ctx;
+int batch_record_pass(Ctx& c, const VmParams& P, const VmFinal& F, int dtype, int tier);
+void batch_record_drop(Ctx& c);
 
 enum PartKind { PK_NONE = 0, PK_TILING = 1, PK_IMAGE = 2 };
 
@@ -161,6 +164,7 @@ struct Ctx {
 
   dfx_stats stats{};
   void* server = nullptr;   // continuous-batching CG server, if started
+  void* batch_rec = nullptr;  // recording into a batch (batch.cpp): passes are kept, not launched
   // allocation-free flush: the device's scratch array, the mode flag, and the
   // device frees deferred while the mode is on
   void* scratch = nullptr;
