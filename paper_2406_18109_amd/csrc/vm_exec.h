@@ -38,6 +38,12 @@ template <typename T> __device__ __forceinline__ T d_pow(T x, T y);
 template <> __device__ __forceinline__ double d_pow<double>(double x, double y) { return pow(x, y); }
 template <> __device__ __forceinline__ float d_pow<float>(float x, float y) { return powf(x, y); }
 
+// FP64 transcendental handlers evaluate the E values of a step in
+// DFX_MATH_SPLIT groups (fewer live temporaries per group)
+#ifndef DFX_MATH_SPLIT
+#define DFX_MATH_SPLIT 1
+#endif
+
 template <typename T> __device__ __forceinline__ T d_max(T x, T y) { return (x > y || x != x) ? x : y; }
 template <typename T> __device__ __forceinline__ T d_min(T x, T y) { return (x < y || x != x) ? x : y; }
 template <typename T> __device__ __forceinline__ T d_abs(T x) { return x < (T)0 ? -x : x == (T)0 ? (T)0 : x; }
@@ -210,7 +216,10 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
 // step (row next_row0, known to be MODE_FAST) are issued into L as soon as
 // this step's values are in registers, so they are in flight during the op
 // list and the stores.
-template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS>
+// SPMV_RT (with SPMV): the SpMV prologue runs only for passes that have one
+// (P.spmv), so one instantiation serves SpMV and elementwise passes alike
+// (the batched executor's).
+template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS, bool SPMV_RT = false>
 __device__ __forceinline__ void vm_step(
     const VmParams& P,
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
@@ -289,10 +298,12 @@ __device__ __forceinline__ void vm_step(
   }
   if constexpr (SPMV) {
     static_assert(U == 1, "SpMV steps take one row of the tiling");
-    T y[4];
-    spmv_rows<T, V>(P, row0 * TW, y, scol, sval);
+    if (!SPMV_RT || P.spmv) {
+      T y[4];
+      spmv_rows<T, V>(P, row0 * TW, y, scol, sval);
 #pragma unroll
-    for (int e = 0; e < E; ++e) RSET(NR - 1, e, y[e]);
+      for (int e = 0; e < E; ++e) RSET(NR - 1, e, y[e]);
+    }
   }
 
   // ---- op list: the next instruction's load overlaps the current op --------
@@ -327,10 +338,13 @@ __device__ __forceinline__ void vm_step(
 #define UNW(FN, F)                                                                                 \
   {                                                                                                \
     if constexpr (sizeof(T) == 8) {                                                                \
-      double a_[E];                                                                                \
-      _Pragma("unroll") for (int e = 0; e < E; ++e) a_[e] = gget<T, GS>(G.z[e / GS], e % GS);     \
-      FN(a_);                                                                                      \
-      _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, (T)a_[e]);   \
+      constexpr int EH = E / DFX_MATH_SPLIT;                                                       \
+      _Pragma("unroll") for (int h = 0; h < DFX_MATH_SPLIT; ++h) {                                 \
+        double a_[EH];                                                                             \
+        _Pragma("unroll") for (int e = 0; e < EH; ++e) a_[e] = gget<T, GS>(G.z[(h * EH + e) / GS], (h * EH + e) % GS); \
+        FN(a_);                                                                                    \
+        _Pragma("unroll") for (int e = 0; e < EH; ++e) gset<T, GS>(G.z[(h * EH + e) / GS], (h * EH + e) % GS, (T)a_[e]); \
+      }                                                                                            \
     } else {                                                                                       \
       _Pragma("unroll") for (int e = 0; e < E; ++e)                                                \
         gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS)));                    \
@@ -525,14 +539,24 @@ void vm_kernel(const VmParams P) {
 
   // Arithmetic passes are stream-bound: their loads are software-pipelined
   // one step ahead inside a tile (up to four streams: the wider bucket would
-  // lose a wave of occupancy to the prefetch registers).
+  // lose a wave of occupancy to the prefetch registers).  Transcendental
+  // passes are not (DFX_HEAVY_PF=1 pipelines them too: 2 % faster for
+  // Black-Scholes FP64 with the load buffer, but the buffer costs a wave).
 #ifndef DFX_PREFETCH_MAX_STREAMS
 #define DFX_PREFETCH_MAX_STREAMS 4
 #endif
-  constexpr bool PF = !S::HEAVY && !SPMV && NINB <= DFX_PREFETCH_MAX_STREAMS;
-  // Transcendental kernels also load through vm_load (padding slots skipped),
-  // without prefetching: their time goes to arithmetic.
-  constexpr bool SPLIT = PF || (S::HEAVY && !SPMV);
+#ifndef DFX_HEAVY_PF
+#define DFX_HEAVY_PF 0
+#endif
+  constexpr bool PF = !SPMV && NINB <= DFX_PREFETCH_MAX_STREAMS && (!S::HEAVY || DFX_HEAVY_PF);
+  // FP32 transcendental kernels load through vm_load (padding slots
+  // skipped).  The FP64 ones load straight into the register file: without
+  // the separate load buffer they fit three waves per SIMD instead of two
+  // (1.05 against 1.26 ms for Black-Scholes FP64 over 2^26 options).
+#ifndef DFX_HEAVY_SPLIT
+#define DFX_HEAVY_SPLIT (sizeof(T) == 4)
+#endif
+  constexpr bool SPLIT = PF || (S::HEAVY && !SPMV && DFX_HEAVY_SPLIT);
   T L[NINB][E];
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int64_t tr = t / P.strips;
