@@ -77,6 +77,38 @@ def timed_steps(torch, stream, step, K):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
+# FP64 VALU issue peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz lane-
+# instructions per second (an FMA is one instruction, two flops: 78.6 TFLOP/s)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+
+
+def alu_roof(n, kernel_s):
+    """The ALU roof of the Black-Scholes FP64 pass from the committed counter
+    summary (profiles/traffic.json, taken on the current kernel source):
+    `math_valu_per_option` is the VALU instruction count of the op list's
+    arithmetic alone (a straight-line evaluation of the same chain with the
+    same math routines), `valu_per_option` what the op-list kernel executes
+    (SQ_INSTS_VALU x 64 / options).  Floors at the VALU issue peak, and the
+    achieved rate of the math instructions.  None without a current summary."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        e = json.load(fh).get("bs_f64_fused")
+    if not e or e.get("kernel_hash") != kernel_source_hash() or "math_valu_per_option" not in e:
+        return None
+    math_i = e["math_valu_per_option"]
+    cnt = e.get("valu_per_option")
+    ach = math_i * n / kernel_s
+    out = {"unit": "T lane-instr/s", "peak": round(VALU_PEAK_LANE_INSTR / 1e12, 2),
+           "math_valu_per_option": math_i, "math_floor_ms": round(math_i * n / VALU_PEAK_LANE_INSTR * 1e3, 4),
+           "achieved": round(ach / 1e12, 3), "frac": round(ach / VALU_PEAK_LANE_INSTR, 4)}
+    if cnt is not None:
+        out["valu_per_option"] = cnt
+        out["valu_issue_frac"] = round(cnt * n / kernel_s / VALU_PEAK_LANE_INSTR, 4)
+    return out
+
+
 class BSBench:
     def __init__(self, dfx, synth, np, n, dtype, fuse):
         self.np = np
@@ -113,8 +145,32 @@ class BSBench:
         self.ctx.close()
 
 
-def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W):
+def paper_mean(times):
+    """The paper's timing method: drop the fastest and the slowest run,
+    average the rest (12 runs -> mean of 10)."""
+    t = sorted(times)
+    if len(t) > 2:
+        t = t[1:-1]
+    return sum(t) / len(t)
+
+
+def counts(st, units):
+    """Per-unit task and group counts (the paper's task-count table: tasks per
+    iteration issued, fused tasks dispatched) and launches."""
+    return {"tasks_per_iter": st["tasks_dispatched"] / units, "groups_per_iter": st["groups_dispatched"] / units,
+            "launches_per_iter": st["launches"] / units}
+
+
+def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W, runs=0):
+    t0 = time.perf_counter()
     b = BSBench(dfx, synth, np, n, dtype, fuse)
+    setup = time.perf_counter() - t0
+    # the first pass: analysis, lowering and the plan's first launch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step()
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
     for _ in range(max(W, 8) if TUNE else W):
         b.step()
     b.ctx.stats_reset()
@@ -122,11 +178,19 @@ def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W):
     st = b.ctx.stats()
     bytes_per_step = st["alg_bytes"] / K
     launches = st["launches"] / K
+    paper = None
+    if runs:
+        paper = paper_mean([timed_steps(torch, b.ctx.torch_stream, b.step, 10)[0] for _ in range(runs)])
     b.close()
     ev_ms = sum(ev) / len(ev)
-    return {"ms_per_step": wall, "event_ms_per_step": ev_ms, "alg_bytes_per_step": bytes_per_step,
-            "launches_per_step": launches, "gbs": bytes_per_step / (wall * 1e-3) / 1e9,
-            "kernel_gbs": bytes_per_step / (ev_ms * 1e-3) / 1e9}
+    out = {"ms_per_step": wall, "event_ms_per_step": ev_ms, "alg_bytes_per_step": bytes_per_step,
+           "launches_per_step": launches, "gbs": bytes_per_step / (wall * 1e-3) / 1e9,
+           "kernel_gbs": bytes_per_step / (ev_ms * 1e-3) / 1e9, "first_pass_ms": first * 1e3,
+           "analysis_s": st["analysis_seconds"], "tasks_per_pass": st["tasks_dispatched"] / K,
+           "groups_per_pass": st["groups_dispatched"] / K}
+    if paper is not None:
+        out["paper_method_ms_per_step"] = paper
+    return out
 
 
 def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
@@ -134,7 +198,12 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
     G = c.store_create([N, N], "f64")
     c.store_write(G, synth.jacobi_grid(N))
     J = dfx.apps.Jacobi(c, G, N)
-    for _ in range(8 if TUNE else 3):
+    c.sync()
+    t0 = time.perf_counter()
+    J.sweep()
+    c.sync()
+    first = time.perf_counter() - t0
+    for _ in range(8 if TUNE else 2):
         J.sweep()
     c.sync()
     c.stats_reset()
@@ -145,15 +214,19 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
     c.sync()
     dt = (time.perf_counter() - t0) / sweeps
     st = c.stats()
-    out = {"ms_per_sweep": dt * 1e3, "alg_bytes_per_sweep": st["alg_bytes"] / sweeps,
-           "gbs": st["alg_bytes"] / sweeps / dt / 1e9, "launches_per_sweep": st["launches"] / sweeps}
+    out = {"sweeps": sweeps, "ms_per_sweep": dt * 1e3, "alg_bytes_per_sweep": st["alg_bytes"] / sweeps,
+           "gbs": st["alg_bytes"] / sweeps / dt / 1e9, "launches_per_sweep": st["launches"] / sweeps,
+           "first_sweep_ms": first * 1e3}
+    out.update(counts(st, sweeps))
     c.close()
     return out
 
 
-def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg"):
+def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg", runs=0):
     """CG on the Poisson matrix, or BiCGSTAB (solver="bicgstab") on the
-    nonsymmetric convection-diffusion matrix of the same shape."""
+    nonsymmetric convection-diffusion matrix of the same shape.  With
+    `runs`, the timed region is repeated that many times and the paper's
+    method (drop fastest and slowest, mean of the rest) gives ms_per_iter."""
     c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
     if solver == "cg":
         rowptr, col, val = synth.poisson_csr(m, dim)
@@ -170,36 +243,65 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg"):
         hs.append(s)
     del rowptr, col, val
     cg = (dfx.apps.CG if solver == "cg" else dfx.apps.BiCGSTAB)(c, *hs, n)
-    for _ in range(8 if TUNE else 2):
+    c.sync()
+    # first iteration: analysis and lowering of every window (memo misses),
+    # workspaces, first launches
+    t0 = time.perf_counter()
+    cg.iteration()
+    c.sync()
+    first = time.perf_counter() - t0
+    analysis = c.stats()["analysis_seconds"]
+    for _ in range(8 if TUNE else 1):
         cg.iteration()
     c.sync()
     g = None
+    capture = None
     if graph:
+        t0 = time.perf_counter()
         c.graph_begin()
         cg.iteration()
         g = c.graph_end()
+        capture = time.perf_counter() - t0
     c.sync()
+
+    def region():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            if g is not None:
+                c.graph_launch(g)
+            else:
+                cg.iteration()
+        c.sync()
+        return (time.perf_counter() - t0) / iters
+
     c.stats_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        if g is not None:
-            c.graph_launch(g)
-        else:
-            cg.iteration()
-    c.sync()
-    dt = (time.perf_counter() - t0) / iters
+    dt = region()
     st = c.stats()
-    out = {"iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
+    out = {"iters": iters, "iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
            "alg_bytes_per_iter": st["alg_bytes"] / iters,
-           "gbs": st["alg_bytes"] / iters / dt / 1e9, "launches_per_iter": st["launches"] / iters}
+           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3, "analysis_s": analysis}
+    out.update(counts(st, iters))
+    if capture is not None:
+        out["capture_ms"] = capture * 1e3
+        # graph replays do not submit tasks: take the counts from one eager iteration
+        c.stats_reset()
+        cg.iteration()
+        c.sync()
+        st1 = c.stats()
+        out["tasks_per_iter"] = st1["tasks_dispatched"]
+        out["groups_per_iter"] = st1["groups_dispatched"]
+    if runs:
+        times = [region() for _ in range(runs)]
+        out["paper_method_ms_per_iter"] = paper_mean(times) * 1e3
+        out["paper_method_iters_per_s"] = 1.0 / paper_mean(times)
     if g is not None:
         c.graph_destroy(g)
     c.close()
     return out
 
 
-def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph):
+def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph, runs=0):
     """The GMG solver (CG preconditioned by one V(2,2) cycle, injection
     restriction, weighted Jacobi) on the m^2 Poisson problem over nlev
     levels; with graph, one whole iteration is recorded and replayed."""
@@ -216,31 +318,68 @@ def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph):
     del levels
     g = dfx.apps.GMG(c, lev, sizes, up(synth.rhs(m * m, synth.GMG_SEED)))
     c.sync()
+    t0 = time.perf_counter()
     g.iteration()
     c.sync()
+    first = time.perf_counter() - t0
     gid = None
+    capture = None
     if graph:
+        t0 = time.perf_counter()
         c.graph_begin()
         g.iteration()
         gid = c.graph_end()
+        capture = time.perf_counter() - t0
     c.sync()
+
+    def region():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            if gid is not None:
+                c.graph_launch(gid)
+            else:
+                g.iteration()
+        c.sync()
+        return (time.perf_counter() - t0) / iters
+
     c.stats_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        if gid is not None:
-            c.graph_launch(gid)
-        else:
-            g.iteration()
-    c.sync()
-    dt = (time.perf_counter() - t0) / iters
+    dt = region()
     st = c.stats()
-    out = {"iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3, "alg_bytes_per_iter": st["alg_bytes"] / iters,
-           "gbs": st["alg_bytes"] / iters / dt / 1e9, "launches_per_iter": st["launches"] / iters}
+    out = {"iters": iters, "iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
+           "alg_bytes_per_iter": st["alg_bytes"] / iters,
+           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3}
+    out.update(counts(st, iters))
+    if capture is not None:
+        out["capture_ms"] = capture * 1e3
+        c.stats_reset()
+        g.iteration()
+        c.sync()
+        st1 = c.stats()
+        out["tasks_per_iter"] = st1["tasks_dispatched"]
+        out["groups_per_iter"] = st1["groups_dispatched"]
+    if runs:
+        times = [region() for _ in range(runs)]
+        out["paper_method_ms_per_iter"] = paper_mean(times) * 1e3
     if gid is not None:
         c.graph_destroy(gid)
     c.close()
     return out
+
+
+def breakeven(fused, unfused, key_ms, first_key):
+    """One-time cost of fusion (first fused iteration, which analyses and
+    lowers every window, plus the graph capture, less one steady fused
+    iteration), and the iterations after which the fused run is ahead of
+    the unfused one, which pays its own first-iteration cost (the paper's
+    warm-up and breakeven table)."""
+    f_ss, u_ss = fused[key_ms], unfused[key_ms]
+    extra = (fused[first_key] + fused.get("capture_ms", 0.0) - f_ss) - (unfused[first_key] - u_ss)
+    gain = u_ss - f_ss
+    return {"one_time_ms_fused": fused[first_key] + fused.get("capture_ms", 0.0) - f_ss,
+            "one_time_ms_unfused": unfused[first_key] - u_ss,
+            "gain_ms_per_iter": gain,
+            "breakeven_iters": (max(0.0, extra) / gain) if gain > 0 else None}
 
 
 def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0, mats=None):
@@ -341,19 +480,138 @@ def copy_leg(dfx, np, torch, n, K):
             "gbs": 16.0 * n / (ev_ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(synth, wl, np, sample):
-    S, K, T = synth.bs_inputs(sample)
-    r, sig, rv = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL)
-    wl.black_scholes(S[:1000], K[:1000], T[:1000], r, sig, rv)
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        wl.black_scholes(S, K, T, r, sig, rv)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    return sample * 40 / dt / 1e9, reps, dt
+# ---- the oracle on the host's cores ------------------------------------------
+# Timed before anything touches the GPU.  Single-thread: the oracle as it
+# stands.  All-core: the same oracle functions run unchanged by a pool of
+# forked workers over fixed chunks of the same workload (elementwise work
+# split by index ranges, Jacobi by row blocks with their halo rows, CG's SpMV
+# by row blocks); the chunk results are not combined, only timed.
+_POOL_DATA = {}
+
+
+def _host_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return n, model
+
+
+def _bs_chunk(i):
+    from oracle import workloads as wl
+    S, K, T, sc, P = (_POOL_DATA[k] for k in ("S", "K", "T", "sc", "P"))
+    m = S.size // P
+    sl = slice(i * m, (i + 1) * m)
+    wl.black_scholes(S[sl], K[sl], T[sl], *sc)
+    return i
+
+
+def _jac_chunk(i):
+    from oracle import workloads as wl
+    G, P = _POOL_DATA["G"], _POOL_DATA["P"]
+    N = G.shape[0]
+    rows = (N - 2 + P - 1) // P
+    r0 = 1 + i * rows
+    r1 = min(N - 1, r0 + rows)
+    sub = G[r0 - 1:r1 + 1].copy()   # the block's interior rows and one halo row each side
+    wl.jacobi_sweep(sub)
+    return i
+
+
+def _spmv_chunk(i):
+    from oracle import cnum
+    rp, col, val, x, P = (_POOL_DATA[k] for k in ("rp", "col", "val", "x", "P"))
+    n = rp.size - 1
+    rows = (n + P - 1) // P
+    r0, r1 = i * rows, min(n, (i + 1) * rows)
+    lo, hi = int(rp[r0]), int(rp[r1])
+    cnum.spmv((rp[r0:r1 + 1] - lo).astype(np.int32), col[lo:hi], val[lo:hi], x)
+    return i
+
+
+def _timed(fn, reps):
+    """Median wall time of `reps` calls after one untimed call."""
+    fn()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        t.append(time.perf_counter() - t0)
+    t.sort()
+    return t[len(t) // 2]
+
+
+def cpu_baselines(quick=False):
+    """The oracle timed on this host: Black-Scholes (GB/s of the fused pass's
+    algorithmic bytes), one Jacobi sweep of the 8192^2 grid, one CG
+    iteration on 256^3; single-thread and all-core (at most 16 workers, the
+    box's CPU share for one GPU)."""
+    import multiprocessing as mp
+    import numpy as _np
+    global np
+    np = _np
+    import synth
+    from oracle import cnum
+    from oracle import workloads as wl
+    ncpu, model = _host_info()
+    P = max(1, min(16, ncpu))
+    out = {"host_cpus": ncpu, "cpu_model": model, "workers": P}
+    # Black-Scholes: 2^21 options single-thread; P chunks of 2^21 all-core
+    n1 = 1 << 21
+    S, K, T = synth.bs_inputs(n1 * P)
+    sc = wl.bs_scalars(synth.BS_RATE, synth.BS_VOL)
+    reps = 2 if quick else 5
+    t1 = _timed(lambda: wl.black_scholes(S[:n1], K[:n1], T[:n1], *sc), reps)
+    ctx = mp.get_context("fork")
+
+    def all_core(fn):
+        # workers forked after the workload's data is in place (copy on write)
+        with ctx.Pool(P) as pool:
+            return _timed(lambda: pool.map(fn, range(P)), reps_big)
+
+    reps_big = 1 if quick else 2
+    _POOL_DATA.update(S=S, K=K, T=T, sc=sc, P=P)
+    with ctx.Pool(P) as pool:
+        tp = _timed(lambda: pool.map(_bs_chunk, range(P)), reps)
+    out["bs_f64"] = {"options_single": n1, "gbs_single": 40.0 * n1 / t1 / 1e9,
+                     "options_all": n1 * P, "gbs_all": 40.0 * n1 * P / tp / 1e9}
+    log("cpu: black-scholes", out["bs_f64"])
+    del S, K, T
+    _POOL_DATA.clear()
+    # Jacobi: one sweep of 8192^2 (each timed call starts from a copy of the grid)
+    N = 1024 if quick else 8192
+    G = synth.jacobi_grid(N)
+    tj1 = _timed(lambda: wl.jacobi_sweep(G.copy()), reps_big)
+    _POOL_DATA.update(G=G, P=P)
+    tjp = all_core(_jac_chunk)
+    out["jacobi_sweep"] = {"grid": N, "ms_single": tj1 * 1e3, "ms_all": tjp * 1e3}
+    log("cpu: jacobi", out["jacobi_sweep"])
+    del G
+    _POOL_DATA.clear()
+    # CG on 256^3: the set-up and first iteration single-thread; its SpMV
+    # single-thread and all-core
+    m = 64 if quick else 256
+    rp, col, val = synth.poisson_csr(m, 3)
+    b = synth.rhs(m ** 3, synth.CG256_SEED)
+    tc1 = _timed(lambda: wl.cg(rp, col, val, b, 1), reps_big)
+    ts1 = _timed(lambda: cnum.spmv(rp, col, val, b), reps_big)
+    _POOL_DATA.update(rp=rp, col=col, val=val, x=b, P=P)
+    tsp = all_core(_spmv_chunk)
+    out["cg256_iteration"] = {"side": m, "setup_and_first_iteration_ms_single": tc1 * 1e3,
+                              "spmv_ms_single": ts1 * 1e3, "spmv_ms_all": tsp * 1e3}
+    log("cpu: cg", out["cg256_iteration"])
+    _POOL_DATA.clear()
+    return out
 
 
 def serve_main(dfx, synth, np, args):
@@ -381,6 +639,8 @@ def main():
     ap.add_argument("--serve-iters-per-round", type=int, default=0,
                     help="CG iterations per scheduling round (0: the library default)")
     ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timings on the host")
+    ap.add_argument("--quick-cpu", action="store_true", help="small oracle samples (a smoke run of the bench)")
     args = ap.parse_args()
     global TUNE
     TUNE = args.tune
@@ -390,14 +650,20 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    n = 1 << args.log2n
+    K, W = args.steps, args.warmup
+    cpu = None
+    if args.legs not in ("copy", "serve") and not args.no_cpu:
+        # before anything touches the GPU: the pool's workers are forked
+        log("cpu oracle on the host's cores")
+        cpu = cpu_baselines(quick=args.quick_cpu)
+
     import torch
 
     import paper_2406_18109_amd as dfx
     import synth
-    from oracle import workloads as wl
 
-    n = 1 << args.log2n
-    K, W = args.steps, args.warmup
     if args.legs == "copy":
         print(json.dumps(copy_leg(dfx, np, torch, n, K)))
         return
@@ -414,13 +680,18 @@ def main():
     else:
         sel = set(args.legs.split(","))
     log("black-scholes f64 fused n=2^%d" % args.log2n)
-    fused = bs_leg(torch, dfx, synth, np, n, "f64", True, K, W)
+    fused = bs_leg(torch, dfx, synth, np, n, "f64", True, K, W, runs=12 if "bs_f64" in sel else 0)
     log("fused", fused)
     legs = {"bs_f64_fused": fused}
+    log("copy 2^%d doubles (the streaming ceiling)" % args.log2n)
+    copy = copy_leg(dfx, np, torch, n, max(K, 20))
+    legs["copy"] = copy
     if "bs_f64" in sel:
         log("black-scholes f64 unfused")
         legs["bs_f64_unfused"] = bs_leg(torch, dfx, synth, np, n, "f64", False, max(2, K // 5), 1)
-        legs["bs_f64_fused"]["speedup_vs_unfused"] = legs["bs_f64_unfused"]["ms_per_step"] / fused["ms_per_step"]
+        u = legs["bs_f64_unfused"]
+        fused["speedup_vs_unfused"] = u["ms_per_step"] / fused["ms_per_step"]
+        fused["breakeven"] = breakeven(fused, u, "ms_per_step", "first_pass_ms")
     if "bs_f32" in sel:
         log("black-scholes f32 fused / unfused")
         legs["bs_f32_fused"] = bs_leg(torch, dfx, synth, np, n, "f32", True, K, W)
@@ -428,43 +699,62 @@ def main():
         legs["bs_f32_fused"]["speedup_vs_unfused"] = (legs["bs_f32_unfused"]["ms_per_step"] /
                                                      legs["bs_f32_fused"]["ms_per_step"])
     if "jacobi" in sel:
-        log("jacobi 8192^2 fused / unfused")
-        legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, 20, True)
-        legs["jacobi_unfused"] = jacobi_leg(torch, dfx, synth, np, 8192, 5, False)
-        legs["jacobi_fused"]["speedup_vs_unfused"] = (legs["jacobi_unfused"]["ms_per_sweep"] /
-                                                     legs["jacobi_fused"]["ms_per_sweep"])
+        log("jacobi 8192^2 fused (200 sweeps) / unfused")
+        legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, 200, True)
+        legs["jacobi_unfused"] = jacobi_leg(torch, dfx, synth, np, 8192, 10, False)
+        jf, ju = legs["jacobi_fused"], legs["jacobi_unfused"]
+        jf["speedup_vs_unfused"] = ju["ms_per_sweep"] / jf["ms_per_sweep"]
+        jf["breakeven"] = breakeven(jf, ju, "ms_per_sweep", "first_sweep_ms")
     if "cg64" in sel:
-        log("cg 64^2")
-        legs["cg64_unfused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, False, False)
-        legs["cg64_fused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, False)
-        legs["cg64_fused_graph"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, True)
+        log("cg 64^2 (12 runs of 100 iterations each)")
+        legs["cg64_unfused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, False, False, runs=12)
+        legs["cg64_fused"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, False, runs=12)
+        legs["cg64_fused_graph"] = cg_leg(torch, dfx, synth, np, 64, 2, 100, True, True, runs=12)
+        legs["cg64_fused_graph"]["breakeven"] = breakeven(legs["cg64_fused_graph"], legs["cg64_unfused"],
+                                                          "ms_per_iter", "first_iter_ms")
     if "cg256" in sel:
-        log("cg 256^3")
-        legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 30, True, True)
-        legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False)
+        log("cg 256^3 (500 iterations)")
+        legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 500, True, True)
+        legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 20, False, False)
+        cf, cu = legs["cg256_fused_graph"], legs["cg256_unfused"]
+        cf["speedup_vs_unfused"] = cu["ms_per_iter"] / cf["ms_per_iter"]
+        cf["breakeven"] = breakeven(cf, cu, "ms_per_iter", "first_iter_ms")
     if "bicgstab256" in sel:
         log("bicgstab 256^3")
-        legs["bicgstab256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 20, True, True, "bicgstab")
-        legs["bicgstab256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 6, False, False, "bicgstab")
-        legs["bicgstab256_fused_graph"]["speedup_vs_unfused"] = (legs["bicgstab256_unfused"]["ms_per_iter"] /
-                                                                 legs["bicgstab256_fused_graph"]["ms_per_iter"])
+        legs["bicgstab256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 50, True, True, "bicgstab")
+        legs["bicgstab256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 10, False, False, "bicgstab")
+        bf, bu = legs["bicgstab256_fused_graph"], legs["bicgstab256_unfused"]
+        bf["speedup_vs_unfused"] = bu["ms_per_iter"] / bf["ms_per_iter"]
+        bf["breakeven"] = breakeven(bf, bu, "ms_per_iter", "first_iter_ms")
     if "gmg" in sel:
-        log("gmg 1023^2, 9 levels")
-        legs["gmg1023_fused_graph"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 10, True, True)
-        legs["gmg1023_unfused"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 3, False, False)
-        legs["gmg1023_fused_graph"]["speedup_vs_unfused"] = (legs["gmg1023_unfused"]["ms_per_iter"] /
-                                                             legs["gmg1023_fused_graph"]["ms_per_iter"])
+        log("gmg 1023^2, 9 levels (12 runs of 5 iterations)")
+        legs["gmg1023_fused_graph"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 5, True, True, runs=12)
+        legs["gmg1023_unfused"] = gmg_leg(torch, dfx, synth, np, 1023, 9, 5, False, False)
+        gf, gu = legs["gmg1023_fused_graph"], legs["gmg1023_unfused"]
+        gf["speedup_vs_unfused"] = gu["ms_per_iter"] / gf["ms_per_iter"]
+        gf["breakeven"] = breakeven(gf, gu, "ms_per_iter", "first_iter_ms")
     if "serve" in sel:
         log("serving: %d CG solves, %s" % (args.serve_requests, "load sweep" if args.serve_rate is None
                                               else "Poisson arrivals at %.0f/s" % args.serve_rate))
         legs["serve"] = serve_main(dfx, synth, np, args)
 
-    log("cpu oracle sample")
-    sample = 1 << 21
-    cpu_gbs, reps, dt = cpu_baseline(synth, wl, np, sample)
     per_launch = fused["alg_bytes_per_step"] / max(1.0, fused["launches_per_step"])
-    achieved = per_launch / (fused["event_ms_per_step"] * 1e-3) / 1e9
+    kernel_s = fused["event_ms_per_step"] * 1e-3 / max(1.0, fused["launches_per_step"])
+    achieved = per_launch / kernel_s / 1e9
     traffic = measured_traffic("bs_f64_fused", per_launch)
+    hbm_floor = per_launch / (HBM_PEAK_GBS * 1e9)
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "frac_of_copy": round(achieved / copy["gbs"], 4), "copy_gbs": round(copy["gbs"], 1),
+            "hbm_floor_ms": round(hbm_floor * 1e3, 4)}
+    alu = alu_roof(n, kernel_s)
+    if alu is not None:
+        roof["alu"] = alu
+        if alu["math_floor_ms"] * 1e-3 > hbm_floor:
+            # the op list's own arithmetic takes longer at the VALU peak than
+            # its bytes at the HBM peak: the pass is ALU-bound
+            roof.update(bound="alu", achieved=alu["achieved"], peak=alu["peak"], unit=alu["unit"],
+                        frac=alu["frac"], hbm_frac=round(achieved / HBM_PEAK_GBS, 4))
     line = {
         "metric": "fused vs unfused HBM GB/s (% of peak) and CG iters/s on 1 MI355X; p99 solve latency",
         "value": round(fused["gbs"], 2),
@@ -480,12 +770,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "black-scholes fused pass, 2^%d options FP64 (28 index tasks -> 1 kernel)" % args.log2n,
                    "options": n, "tasks_per_pass": 28, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
-        "cpu_baseline": {"value": round(cpu_gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-                         "sample": "%d options x %d reps, FP64 numpy + libm, unfused op by op" % (sample, reps)},
+        "roofline": roof,
         "legs": legs,
     }
+    if cpu is not None:
+        bs = cpu["bs_f64"]
+        line["cpu_baseline"] = {
+            "value": round(bs["gbs_all"], 4), "unit": "GB/s", "cores": cpu["workers"], "kind": "oracle",
+            "sample": "Black-Scholes FP64, %d options in %d fixed chunks (one forked worker each, the oracle "
+                      "unchanged: numpy + libm, unfused op by op); host %s, %d CPUs" %
+                      (bs["options_all"], cpu["workers"], cpu["cpu_model"], cpu["host_cpus"]),
+            "single_thread": {"value": round(bs["gbs_single"], 4), "unit": "GB/s", "cores": 1,
+                              "sample": "%d options" % bs["options_single"]},
+            "jacobi_sweep_8192": cpu["jacobi_sweep"], "cg256_iteration": cpu["cg256_iteration"]}
     print(json.dumps(line))
 
 
