@@ -171,6 +171,7 @@ def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W, runs=0):
     b.step()
     torch.cuda.synchronize()
     first = time.perf_counter() - t0
+    analysis = b.ctx.stats()["analysis_seconds"]
     for _ in range(max(W, 8) if TUNE else W):
         b.step()
     b.ctx.stats_reset()
@@ -186,7 +187,7 @@ def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W, runs=0):
     out = {"ms_per_step": wall, "event_ms_per_step": ev_ms, "alg_bytes_per_step": bytes_per_step,
            "launches_per_step": launches, "gbs": bytes_per_step / (wall * 1e-3) / 1e9,
            "kernel_gbs": bytes_per_step / (ev_ms * 1e-3) / 1e9, "first_pass_ms": first * 1e3,
-           "analysis_s": st["analysis_seconds"], "tasks_per_pass": st["tasks_dispatched"] / K,
+           "analysis_s": analysis, "tasks_per_pass": st["tasks_dispatched"] / K,
            "groups_per_pass": st["groups_dispatched"] / K}
     if paper is not None:
         out["paper_method_ms_per_step"] = paper
@@ -434,6 +435,58 @@ def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0, mats=None):
 SERVE_LOADS = (0.5, 0.8, 0.95)
 
 
+def batch_leg(dfx, synth, np, count, slots, budget):
+    """The serving stream's first `count` solves run as task streams of the
+    persistent batched executor: each solve's CG set-up in its own context,
+    one CG iteration recorded as a repeated body that stops at
+    rho_k <= 1e-16 rho_0 (||r_k|| <= 1e-8 ||b||), every stream in one
+    launch.  Beside it the round-based server on the same requests, all
+    submitted at once (closed loop)."""
+    sides = synth.serve_sides(count)
+    mats = {int(s): synth.poisson_csr(int(s), 2) for s in set(sides.tolist())}
+    b = dfx.Batch(device=0)
+    ctxs = []
+    t0 = time.perf_counter()
+    for i in range(count):
+        side = int(sides[i])
+        c = dfx.Context(device=0, window_size=16)
+        rp, col, val = mats[side]
+        hs = []
+        for a, dt in ((rp, "i32"), (col, "i32"), (val, "f64"), (synth.serve_rhs(i, side * side), "f64")):
+            h = c.store_create(list(a.shape), dt)
+            c.store_write(h, a)
+            hs.append(h)
+        cg = dfx.apps.CG(c, *hs, side * side)
+        r0 = c.store_create([], "f64")
+        none = c.part_none()
+        c.submit("copy", [], [(cg.rho, none, "R"), (r0, none, "W")])
+        c.flush()
+        b.record_begin(c)
+        b.loop_begin(c)
+        cg.iteration()
+        b.record_end(c, max_iter=20000, conv_a=cg.rho, conv_b=r0, tol=1e-16)
+        ctxs.append((c, cg))
+    setup = time.perf_counter() - t0
+    cnt = b.counts()
+    t0 = time.perf_counter()
+    b.run()   # one launch solves every stream (a second run would resume from the solutions)
+    b.wait()
+    wall = time.perf_counter() - t0
+    its = [b.stream_info(i)[0] for i in range(count)]
+    done = sum(1 for i in range(count) if b.stream_info(i)[1] == dfx.Batch.DONE)
+    b.close()
+    for c, _ in ctxs:
+        c.close()
+    out = {"requests": count, "converged": done, "solves_per_s": count / wall, "wall_s": wall,
+           "mean_iterations": float(np.mean(its)), "max_iterations": int(np.max(its)),
+           "record_s": setup, "streams": cnt["streams"], "passes": cnt["passes"], "grid": cnt["grid"]}
+    log("batch", out)
+    srv = serve_leg(dfx, synth, np, count, None, budget, slots, 0, mats)
+    out["server_closed_loop_solves_per_s"] = srv["solves_per_s"]
+    out["speedup_vs_server"] = out["solves_per_s"] / srv["solves_per_s"]
+    return out
+
+
 def serve_sweep(dfx, synth, np, count, budget, slots, ipr=0):
     """Saturation throughput from a closed-loop run (all requests at once),
     then Poisson arrivals at 0.5, 0.8 and 0.95 of it; the leg's p50/p99 are
@@ -630,8 +683,10 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="enable the library's launch-shape tuner (warm-ups extended to 8 executions)")
     ap.add_argument("--legs", default="all",
-                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,bicgstab256,gmg,serve")
+                    help="all | headline | serve | copy | comma-separated bs_f64,bs_f32,jacobi,cg64,cg256,bicgstab256,gmg,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--batch-requests", type=int, default=256,
+                    help="serving solves run by the batched executor in one launch")
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="fixed Poisson arrival rate; default: a saturation run, then 0.5/0.8/0.95 of it")
     ap.add_argument("--serve-slots", type=int, default=256)
@@ -639,6 +694,8 @@ def main():
     ap.add_argument("--serve-iters-per-round", type=int, default=0,
                     help="CG iterations per scheduling round (0: the library default)")
     ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--jacobi-sweeps", type=int, default=200, help="fused Jacobi sweeps timed (the config's 200)")
+    ap.add_argument("--cg256-iters", type=int, default=500, help="CG 256^3 iterations timed (the config's 500)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timings on the host")
     ap.add_argument("--quick-cpu", action="store_true", help="small oracle samples (a smoke run of the bench)")
     args = ap.parse_args()
@@ -672,9 +729,9 @@ def main():
         print(json.dumps(out))
         return
     # legs: "all" (the default line), "headline", or a comma-separated list of
-    # bs_f64, bs_f32, jacobi, cg64, cg256, bicgstab256, gmg, serve
+    # bs_f64, bs_f32, jacobi, cg64, cg256, bicgstab256, gmg, batch, serve
     if args.legs == "all":
-        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "bicgstab256", "gmg", "serve"}
+        sel = {"bs_f64", "bs_f32", "jacobi", "cg64", "cg256", "bicgstab256", "gmg", "batch", "serve"}
     elif args.legs == "headline":
         sel = set()
     else:
@@ -699,8 +756,8 @@ def main():
         legs["bs_f32_fused"]["speedup_vs_unfused"] = (legs["bs_f32_unfused"]["ms_per_step"] /
                                                      legs["bs_f32_fused"]["ms_per_step"])
     if "jacobi" in sel:
-        log("jacobi 8192^2 fused (200 sweeps) / unfused")
-        legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, 200, True)
+        log("jacobi 8192^2 fused (%d sweeps) / unfused" % args.jacobi_sweeps)
+        legs["jacobi_fused"] = jacobi_leg(torch, dfx, synth, np, 8192, args.jacobi_sweeps, True)
         legs["jacobi_unfused"] = jacobi_leg(torch, dfx, synth, np, 8192, 10, False)
         jf, ju = legs["jacobi_fused"], legs["jacobi_unfused"]
         jf["speedup_vs_unfused"] = ju["ms_per_sweep"] / jf["ms_per_sweep"]
@@ -713,8 +770,8 @@ def main():
         legs["cg64_fused_graph"]["breakeven"] = breakeven(legs["cg64_fused_graph"], legs["cg64_unfused"],
                                                           "ms_per_iter", "first_iter_ms")
     if "cg256" in sel:
-        log("cg 256^3 (500 iterations)")
-        legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, 500, True, True)
+        log("cg 256^3 (%d iterations)" % args.cg256_iters)
+        legs["cg256_fused_graph"] = cg_leg(torch, dfx, synth, np, 256, 3, args.cg256_iters, True, True)
         legs["cg256_unfused"] = cg_leg(torch, dfx, synth, np, 256, 3, 20, False, False)
         cf, cu = legs["cg256_fused_graph"], legs["cg256_unfused"]
         cf["speedup_vs_unfused"] = cu["ms_per_iter"] / cf["ms_per_iter"]
@@ -733,6 +790,10 @@ def main():
         gf, gu = legs["gmg1023_fused_graph"], legs["gmg1023_unfused"]
         gf["speedup_vs_unfused"] = gu["ms_per_iter"] / gf["ms_per_iter"]
         gf["breakeven"] = breakeven(gf, gu, "ms_per_iter", "first_iter_ms")
+    if "batch" in sel:
+        log("batched executor: %d serving solves in one launch, against the server" % args.batch_requests)
+        legs["batch"] = batch_leg(dfx, synth, np, args.batch_requests, args.serve_slots,
+                                  int(args.serve_budget_gb * (1 << 30)))
     if "serve" in sel:
         log("serving: %d CG solves, %s" % (args.serve_requests, "load sweep" if args.serve_rate is None
                                               else "Poisson arrivals at %.0f/s" % args.serve_rate))

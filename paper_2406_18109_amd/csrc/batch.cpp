@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,6 +51,7 @@ struct dfx_batch {
   bool started = false;
   bool pending = false;   // a launch not yet waited for
   int grid = 0;
+  int n_xcd = 1;          // XCDs (L2 domains) of the device; stream s runs on XCD s % n_xcd
   std::string err;
 };
 
@@ -81,6 +83,7 @@ int batch_record_pass(Ctx& c, const VmParams& P, const VmFinal& F, int dtype, in
     return DFX_OK;
   }
   B.P.tiles_per_wave = tpw;
+  B.P.sp_coop = 0;   // the batch kernel computes SpMV rows per wave
   B.n_runs = (int32_t)((P.n_tiles + tpw - 1) / tpw);
   for (int k = 0; k < VM_MAXRED; ++k) B.P.red_partials[k] = nullptr;
   for (int k = 0; k < F.n_red; ++k) {
@@ -118,7 +121,10 @@ int dfx_batch_create(int32_t device, void* stream, dfx_batch** out) {
     return DFX_EHIP;
   }
   const int w = batch_waves_per_cu();
-  b->grid = std::max(1, n_cu * std::max(w, 4) / (BLOCK / WAVE));
+  // every block resident; gfx950 has 32 compute units per XCD, and blocks
+  // are dispatched to the XCDs in turn, so each XCD gets grid / n_xcd of them
+  b->n_xcd = std::max(1, std::min(BATCH_MAX_XCD, n_cu / 32));
+  b->grid = std::max(b->n_xcd, n_cu * std::max(w, 4) / (BLOCK / WAVE));
   *out = b;
   return DFX_OK;
 }
@@ -258,7 +264,7 @@ int dfx_batch_run(dfx_batch* b, int32_t round_limit, int32_t restart) {
     restart = 1;   // new streams start from their first pass
   }
   if (!b->d_ctl && hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess) return bfail(b, DFX_ENOMEM, "batch control");
-  uint32_t settled = 0;
+  size_t settled = 0;
   for (auto& st : b->streams) {
     if (restart || !b->started) {
       st.claim = 0;
@@ -270,12 +276,20 @@ int dfx_batch_run(dfx_batch* b, int32_t round_limit, int32_t restart) {
       st.claim = (st.claim >> 32) << 32;   // reopen the next pass
     }
     st.round_iters = 0;
-    if (st.status != BS_RUNNING) settled += 1;
+    if (st.status != BS_RUNNING) {
+      settled += 1;
+      st.claim = ((st.claim >> 32) << 32) | 0x80000000ull;   // closed: nothing to claim
+    }
   }
   std::memset(&b->ctl, 0, sizeof(b->ctl));
   b->ctl.n_streams = (uint32_t)ns;
-  b->ctl.n_settled = settled;
+  b->ctl.n_xcd = (uint32_t)b->n_xcd;
   b->ctl.round_limit = std::max(0, round_limit);
+  for (size_t i = 0; i < ns; ++i) {
+    BatchXcd& X = b->ctl.x[i % b->n_xcd];
+    X.n_streams += 1;
+    if (b->streams[i].status != BS_RUNNING) X.n_settled += 1;
+  }
   b->started = true;
   // order after the recording contexts' work (writes of inputs, earlier passes)
   if (hipDeviceSynchronize() != hipSuccess) return bfail(b, DFX_EHIP, "device synchronise before the batch");
@@ -299,7 +313,23 @@ int dfx_batch_wait(dfx_batch* b) {
           hipSuccess ||
       hipMemcpy(&b->ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost) != hipSuccess)
     return bfail(b, DFX_EHIP, "batch state read-back");
-  if (b->ctl.error) return bfail(b, DFX_EHIP, "batch stopped: no pass completed for a long time (stall detector)");
+  for (int x = 0; x < b->n_xcd; ++x)
+    if (b->ctl.x[x].error) {
+      std::string m = "batch stopped: no pass completed for a long time (stall detector); XCD ids seen 0x";
+      char buf[512];
+      std::snprintf(buf, sizeof(buf), "%x; waves per XCD id:", b->ctl.xcc_seen);
+      m += buf;
+      for (int k = 0; k < 16; ++k) {
+        std::snprintf(buf, sizeof(buf), " %u", b->ctl.waves[k]);
+        m += buf;
+      }
+      for (int k = 0; k < b->n_xcd; ++k) {
+        std::snprintf(buf, sizeof(buf), "; xcd %d: %u streams, %u settled, %u passes, error %d", k,
+                      b->ctl.x[k].n_streams, b->ctl.x[k].n_settled, b->ctl.x[k].progress, b->ctl.x[k].error);
+        m += buf;
+      }
+      return bfail(b, DFX_EHIP, m);
+    }
   return DFX_OK;
 }
 

@@ -6,9 +6,10 @@
 // pass0 + n_pre + n_body) repeat up to max_iter times, stopping early when a
 // 0-d FP64 value falls to tol times another.  One persistent launch runs every
 // stream: each wave repeatedly claims a work item (stream, current pass, tile
-// run) and executes it; the wave that finishes a pass's last run reduces the
-// pass's tile sums with the canonical tree and advances the stream.  No wave
-// waits for another: a wave with nothing to claim looks at other streams.
+// run) of a stream of its XCD and executes it; the wave that finishes a
+// pass's last run reduces the pass's tile sums with the canonical tree and
+// advances the stream.  No wave waits for another: a wave with nothing to
+// claim looks at the XCD's other streams.
 #pragma once
 #include <stdint.h>
 
@@ -42,13 +43,24 @@ struct BatchStream {
   int32_t status;                // BatchStatus
 };
 
-struct BatchCtl {
-  uint32_t n_streams;
-  uint32_t n_settled;            // streams done or paused in this launch
-  uint32_t progress;             // passes completed (any stream): the stall detector's clock
+// Streams are pinned to XCDs: stream s runs on the compute units of XCD
+// s % n_xcd, whose L2 is the coherence point of everything the stream's
+// waves exchange inside a launch.  Each XCD's counters sit in their own
+// 256-byte line.
+constexpr int BATCH_MAX_XCD = 8;
+struct BatchXcd {
+  uint32_t n_streams;            // streams of this XCD
+  uint32_t n_settled;            // of them, done or paused in this launch
+  uint32_t progress;             // passes completed: the stall detector's clock
   int32_t error;                 // 1: the stall detector fired
+  uint32_t pad[60];
+};
+struct BatchCtl {
+  BatchXcd x[BATCH_MAX_XCD];
+  uint32_t n_streams, n_xcd;
   int32_t round_limit;           // > 0: a stream pauses after this many repetitions in one launch
-  int32_t pad;
+  uint32_t xcc_seen;             // bit k: some wave ran on XCD k (diagnostics)
+  uint32_t waves[16];            // waves that started, per XCD id (diagnostics)
 };
 
 }  // namespace dfx

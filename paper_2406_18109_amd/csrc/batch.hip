@@ -6,10 +6,10 @@
 // the run done.  The wave that finishes a pass's last run reduces the tile
 // sums with the canonical pairwise tree (the same tree the two-launch path
 // evaluates, so every result is bit-identical to a solo run), writes the 0-d
-// results, and advances the stream to its next pass.  Passes of one stream
-// are ordered by release/acquire at agent scope around those atomics; values
-// written inside the launch (0-d results, tile sums) are read with vector or
-// atomic loads, never through the scalar cache.
+// results, and advances the stream to its next pass.  A stream runs on one
+// XCD; its passes are ordered by agent-scope release/acquire (xcd_release,
+// xcd_acquire); values written inside the launch (0-d results, tile sums)
+// are read with vector or atomic loads, never through the scalar cache.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,10 +29,30 @@ constexpr int BHV = 1, BNR = VM_NREG_LIGHT, BNINB = 6;
 typedef Shape<BT, BHV, true, BNR, 0> BS;
 typedef GVec<BT, BS::GS>::type bgvec;
 
-__device__ __forceinline__ double ld_relaxed(const double* p) {
-  const unsigned long long u =
-      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(double, u);
+// Synchronisation.  Streams are pinned to XCDs (so a wave scans only its
+// XCD's streams and a stream's data stays in that XCD's L2), but ordering
+// follows the HIP memory model at agent scope: a run's stores are released
+// by an agent-scope fence before its done count, and a claim or a completed
+// count is followed by an agent-scope acquire fence.  Control words are
+// agent-scope atomics.  (A lighter protocol that kept every exchange inside
+// the XCD's L2, with an L1 invalidate as the only acquire, broke parity on
+// the GPU and is not used.)
+__device__ __forceinline__ void xcd_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void xcd_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+template <typename U> __device__ __forceinline__ U xload(U* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U> __device__ __forceinline__ void xstore(U* p, U v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U> __device__ __forceinline__ U xadd(U* p, U v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A data word written inside the launch (a 0-d result), read after an
+// acquire: an atomic load, never the scalar cache.
+__device__ __forceinline__ double load_data_f64(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
 }
 
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v) {
@@ -85,7 +105,7 @@ __device__ void run_tiles(const BatchPass& B, const BatchStream& st, int64_t r, 
   VmState<BT, BS::NG, BS::GS> G;
   // broadcast operands: 0-d stores, possibly written earlier in this launch
   for (int k = 0; k < P.n_bc; ++k) {
-    const bgvec v = (bgvec)ld_relaxed((const double*)P.bc[k]);
+    const bgvec v = (bgvec)load_data_f64((const double*)P.bc[k]);
     const int rr = P.bc_reg[k];
     constexpr int NG = BS::NG;
     FOR_G(Rg[rr] = v;)
@@ -131,9 +151,9 @@ __device__ void run_tiles(const BatchPass& B, const BatchStream& st, int64_t r, 
   }
 }
 
-// Stall detector: a wave that finds nothing to claim while no pass of any
-// stream has completed for this many ticks of the 100 MHz constant clock
-// (2 s) ends the launch with an error.
+// Stall detector: a wave that finds nothing to claim while no pass of its
+// XCD's streams has completed for this many ticks of the 100 MHz constant
+// clock (2 s) ends the launch with an error.
 #ifndef DFX_BATCH_STALL_TICKS
 #define DFX_BATCH_STALL_TICKS 200000000ull
 #endif
@@ -144,49 +164,68 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
   __shared__ double sp_val[BLOCK / WAVE][SP_CAP];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const uint32_t ns = ctl->n_streams;
+  // this wave's XCD (hardware register XCC_ID)
+  const uint32_t xcc = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)));
+  const uint32_t nxcd = ctl->n_xcd;
+  if (lane == 0) {
+    __hip_atomic_fetch_or(&ctl->xcc_seen, 1u << (xcc & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&ctl->waves[xcc & 15], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (xcc >= nxcd) return;
+  BatchXcd& X = ctl->x[xcc];
+  const uint32_t ns = X.n_streams;   // streams xcc, xcc + nxcd, ...
+  if (ns == 0) return;
   const int gw = blockIdx.x * (BLOCK / WAVE) + wib;
-  uint32_t s = (uint32_t)gw % ns;
+  uint32_t s = ((uint32_t)gw / nxcd) % ns;   // index among this XCD's streams
   uint32_t seen_progress = 0;
   unsigned long long since = __builtin_amdgcn_s_memrealtime();
   for (;;) {
     uint32_t settled = 0, prog = 0;
     int err = 0;
     if (lane == 0) {
-      settled = __hip_atomic_load(&ctl->n_settled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      prog = __hip_atomic_load(&ctl->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      err = __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      settled = xload(&X.n_settled);
+      prog = xload(&X.progress);
+      err = xload(&X.error);
     }
     settled = __builtin_amdgcn_readfirstlane(settled);
     prog = __builtin_amdgcn_readfirstlane(prog);
     err = __builtin_amdgcn_readfirstlane(err);
     if (settled >= ns || err) break;
-    // find a claimable run, starting with the stream this wave last served
+    // find a claimable run: the lanes look at 64 of this XCD's streams at
+    // once (lane l at stream s + l, so the stream this wave last served comes
+    // first); a settled stream's claim word is closed, so one load per stream
+    // decides.  Then lane 0 claims from the candidates in lane order.
     int sid = -1, pidx = 0;
-    uint32_t run = 0, gen = 0;
-    for (uint32_t j = 0; j < ns; ++j) {
-      const uint32_t q = s + j < ns ? s + j : s + j - ns;
-      BatchStream& st = streams[q];
-      unsigned long long w = 0;
-      int32_t status = 0;
-      if (lane == 0) {
-        status = __hip_atomic_load(&st.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        w = __hip_atomic_load(&st.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t run = 0, gen = 0, sl = s;
+    for (uint32_t base = 0; base < ns && sid < 0; base += WAVE) {
+      const uint32_t j = base + lane;
+      uint32_t q = s + j;
+      q = q < ns ? q : q - ns;   // s < ns and j < ns below, so one wrap suffices
+      bool can = false;
+      if (j < ns) {
+        const BatchStream& stl = streams[(size_t)q * nxcd + xcc];
+        const unsigned long long w = xload(&stl.claim);
+        const int p = pass_of(stl, (uint32_t)(w >> 32));
+        can = p >= 0 && (uint32_t)w < (uint32_t)passes[p].n_runs;
       }
-      status = __builtin_amdgcn_readfirstlane(status);
-      if (status != BS_RUNNING) continue;
-      w = bcast64(w);
-      int p = pass_of(st, (uint32_t)(w >> 32));
-      if (p < 0 || (uint32_t)w >= (uint32_t)passes[p].n_runs) continue;
-      if (lane == 0) w = __hip_atomic_fetch_add(&st.claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      w = bcast64(w);
-      p = pass_of(st, (uint32_t)(w >> 32));
-      if (p >= 0 && (uint32_t)w < (uint32_t)passes[p].n_runs) {
-        sid = (int)q;
-        pidx = p;
-        run = (uint32_t)w;
-        gen = (uint32_t)(w >> 32);
-        break;
+      unsigned long long m = __ballot(can);
+      while (m != 0ull) {
+        const int L = (int)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const uint32_t qL = __builtin_amdgcn_readfirstlane(__shfl(q, L, WAVE));
+        BatchStream& st = streams[(size_t)qL * nxcd + xcc];
+        unsigned long long w = 0;
+        if (lane == 0) w = xadd(&st.claim, 1ull);
+        w = bcast64(w);
+        const int p = pass_of(st, (uint32_t)(w >> 32));
+        if (p >= 0 && (uint32_t)w < (uint32_t)passes[p].n_runs) {
+          sid = (int)((size_t)qL * nxcd + xcc);
+          sl = qL;
+          pidx = p;
+          run = (uint32_t)w;
+          gen = (uint32_t)(w >> 32);
+          break;
+        }
       }
     }
     if (sid < 0) {
@@ -197,38 +236,38 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
         seen_progress = prog;
         since = now;
       } else if (now - since > DFX_BATCH_STALL_TICKS) {
-        if (lane == 0) __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) xstore(&X.error, 1);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    s = (uint32_t)sid;
+    s = sl;
     BatchStream& st = streams[sid];
     const BatchPass& B = passes[pidx];
     // acquire: the stream's earlier passes are visible to every lane
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    xcd_acquire();
     run_tiles(B, st, run, sp_col[wib], sp_val[wib]);
     since = __builtin_amdgcn_s_memrealtime();
     // release every lane's stores of this run, then count it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    xcd_release();
     uint32_t d = 0;
-    if (lane == 0) d = __hip_atomic_fetch_add(&st.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) d = xadd(&st.done, 1u);
     d = __builtin_amdgcn_readfirstlane(d);
     if (d + 1 != (uint32_t)B.n_runs) continue;
     // ---- the last run of the pass: reductions, then advance the stream ------
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    xcd_acquire();
     const VmParams& P = B.P;
     double* chunk = st.tsum + (int64_t)VM_MAXRED * st.tsum_stride;
     for (int k = 0; k < P.n_red; ++k) {
       const double v = wave_tree(st.tsum + k * st.tsum_stride, P.n_tiles, chunk, lane);
       if (lane == 0) {
         double* res = (double*)B.result[k];
-        const double old = ld_relaxed(res);
+        const double old = load_data_f64(res);
         *res = B.init[k] ? v : old + v;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    xcd_release();
     int32_t next_status = BS_RUNNING;
     const uint32_t g1 = gen + 1;
     if (st.n_body == 0) {
@@ -238,16 +277,16 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
       // counters now: the stream's next pass is not yet published)
       int32_t it = 0, rit = 0;
       if (lane == 0) {
-        it = __hip_atomic_load(&st.iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-        rit = __hip_atomic_load(&st.round_iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-        __hip_atomic_store(&st.iters, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st.round_iters, rit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it = xload(&st.iters) + 1;
+        rit = xload(&st.round_iters) + 1;
+        xstore(&st.iters, it);
+        xstore(&st.round_iters, rit);
       }
       it = __builtin_amdgcn_readfirstlane(it);
       rit = __builtin_amdgcn_readfirstlane(rit);
       bool stop = it >= st.max_iter;
       if (!stop && st.conv_a) {
-        const double a = ld_relaxed(st.conv_a), b = ld_relaxed(st.conv_b);
+        const double a = load_data_f64(st.conv_a), b = load_data_f64(st.conv_b);
         stop = a <= st.tol * b;
       }
       if (stop) next_status = BS_DONE;
@@ -256,16 +295,12 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
       next_status = BS_DONE;
     }
     if (lane == 0) {
-      __hip_atomic_store(&st.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (next_status != BS_RUNNING) {
-        __hip_atomic_store(&st.status, next_status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st.claim, ((unsigned long long)g1 << 32) | CLAIM_CLOSED, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&ctl->n_settled, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&st.claim, (unsigned long long)g1 << 32, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __hip_atomic_fetch_add(&ctl->progress, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      xstore(&st.done, 0u);
+      if (next_status != BS_RUNNING) xstore(&st.status, next_status);
+      xcd_release();
+      xstore(&st.claim, ((unsigned long long)g1 << 32) | (next_status != BS_RUNNING ? CLAIM_CLOSED : 0ull));
+      if (next_status != BS_RUNNING) xadd(&X.n_settled, 1u);
+      xadd(&X.progress, 1u);
     }
   }
 }

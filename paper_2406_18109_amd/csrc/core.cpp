@@ -1013,6 +1013,46 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   out.unit_cols = 1;
   for (auto& s : out.ins) out.unit_cols &= s.s_col == 1;
   for (auto& s : out.outs) out.unit_cols &= s.s_col == 1;
+  // Stencil staging (arithmetic 2-D passes): three or more input streams
+  // that are views of one store with the same row stride, unit column
+  // stride and origins within a 3 x 3 window are read through LDS.
+  out.st_cs = -1;
+  out.st_on.assign(out.ins.size(), 0);
+  out.st_dr.assign(out.ins.size(), 0);
+  out.st_dc.assign(out.ins.size(), 0);
+  if (kind == 0 && sp.rank == 2 && tier == TIER_ARITH) {
+    std::map<int, std::vector<int>> by_store;
+    for (size_t a = 0; a < out.ins.size(); ++a) by_store[out.ins[a].cstore].push_back((int)a);
+    for (auto& kv : by_store) {
+      const std::vector<int>& m = kv.second;
+      if (m.size() < 3 || m.size() <= (size_t)std::count(out.st_on.begin(), out.st_on.end(), 1)) continue;
+      const int64_t srow = out.ins[m[0]].s_row;
+      bool ok = srow > 0;
+      int64_t r0 = INT64_MAX, c0 = INT64_MAX;
+      for (int a : m) {
+        const PStream& q = out.ins[a];
+        ok = ok && q.s_col == 1 && q.s_row == srow && q.off >= 0;
+        if (!ok) break;
+        r0 = std::min(r0, q.off / srow);
+        c0 = std::min(c0, q.off % srow);
+      }
+      for (int a : m) {
+        if (!ok) break;
+        const int64_t dr = out.ins[a].off / srow - r0, dc = out.ins[a].off % srow - c0;
+        ok = dr <= 2 && dc <= 2;
+      }
+      if (!ok) continue;
+      out.st_cs = kv.first;
+      out.st_off0 = r0 * srow + c0;
+      out.st_srow = srow;
+      std::fill(out.st_on.begin(), out.st_on.end(), 0);
+      for (int a : m) {
+        out.st_on[a] = 1;
+        out.st_dr[a] = (int8_t)(out.ins[a].off / srow - r0);
+        out.st_dc[a] = (int8_t)(out.ins[a].off % srow - c0);
+      }
+    }
+  }
   // launch shape: contiguous tile chunks per wave
   // (a power of two, so that each block's tiles form an aligned subtree of
   // the reduction tree)
@@ -1054,10 +1094,11 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   if (trace_level() > 0) {
     std::fprintf(stderr,
                  "dfx: pass kind=%d %s tier=%d regs=%d code=%zu in=%zu out=%zu bc=%zu red=%zu tiles=%lld "
-                 "tiles/wave=%lld grid=%d alg_bytes=%lld\n",
+                 "tiles/wave=%lld grid=%d alg_bytes=%lld staged=%d\n",
                  kind, dtype == DFX_F64 ? "f64" : "f32", out.tier, out.nreg, out.code.size(), out.ins.size(),
                  out.outs.size(), out.bc_cstore.size(), out.red_cstore.size(), (long long)out.n_tiles,
-                 (long long)out.tiles_per_wave, out.grid, (long long)out.alg_bytes);
+                 (long long)out.tiles_per_wave, out.grid, (long long)out.alg_bytes,
+                 (int)std::count(out.st_on.begin(), out.st_on.end(), 1));
     if (trace_level() > 1)
       for (auto& K : out.code)
         std::fprintf(stderr, "dfx:   op=%u flags=%u slot=%u post=%u dst=%u a=%u b=%u c=%u imm=%08x%08x\n",
@@ -1159,6 +1200,15 @@ static void release_plan(Ctx& c, Plan& plan) {
     if (p.ev1) (void)hipEventDestroy(p.ev1);
     p.ev0 = p.ev1 = nullptr;
   }
+}
+
+// Stencil staging on (default) unless DFX_STENCIL=0.
+static bool stencil_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("DFX_STENCIL");
+    return !(e && e[0] == '0');
+  }();
+  return on;
 }
 
 static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
@@ -1296,8 +1346,27 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     // (DFX_SPMV_STAGE=0 or 1 overrides the choice)
     const char* st = std::getenv("DFX_SPMV_STAGE");
     P.sp_stage = st && (st[0] == '0' || st[0] == '1') ? st[0] == '1' : p.n_tiles >= 256;
+    // a one-tile pass is one block: its four waves compute the rows together
+    // (DFX_SPMV_COOP=0 or 1 overrides)
+    const char* co = std::getenv("DFX_SPMV_COOP");
+    P.sp_coop = (p.n_tiles == 1 && p.grid == 1) &&
+                (co && (co[0] == '0' || co[0] == '1') ? co[0] == '1' : true);
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
+  P.st_n = 0;
+  if (p.st_cs >= 0 && p.st_cs < (int)order.size() && stencil_enabled() && p.st_on.size() == p.ins.size() && p.st_dr.size() == p.ins.size() &&
+      p.st_dc.size() == p.ins.size()) {
+    const StoreRec& ss = S(p.st_cs);
+    for (size_t a = 0; a < p.ins.size(); ++a) {
+      P.st_on[a] = p.st_on[a];
+      P.st_dr[a] = p.st_dr[a];
+      P.st_dc[a] = p.st_dc[a];
+      P.st_n += p.st_on[a];
+    }
+    P.st_base = (const char*)ss.ptr + p.st_off0 * (int64_t)es;
+    P.st_srow = p.st_srow;
+    P.st_lim = ss.elems - p.st_off0;
+  }
   if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
   int e = launch_vm(P, p.dtype == DFX_F64, p.tier, pick_rows(c, p), c.stream);
@@ -1508,6 +1577,7 @@ template <class IO, class P> void pass_fields(IO& io, P& q) {
   io.vec(q.red_cstore); io.vec(q.red_init);
   io.v(q.spmv_rowptr); io.v(q.spmv_col); io.v(q.spmv_val); io.v(q.spmv_x);
   io.vec(q.code); io.vec(q.imm); io.v(q.alg_bytes); io.vec(q.tune_cand);
+  io.v(q.st_cs); io.v(q.st_off0); io.v(q.st_srow); io.vec(q.st_on); io.vec(q.st_dr); io.vec(q.st_dc);
 }
 }  // namespace
 

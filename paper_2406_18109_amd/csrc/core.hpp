@@ -108,6 +108,10 @@ struct PassPlan {
   std::vector<int> red_cstore;
   std::vector<int> red_init;
   int spmv_rowptr = -1, spmv_col = -1, spmv_val = -1, spmv_x = -1;
+  // stencil staging: input streams that are shifted views of store st_cs
+  int st_cs = -1;
+  int64_t st_off0 = 0, st_srow = 0;   // window origin (element offset) and row stride
+  std::vector<int8_t> st_on, st_dr, st_dc;
   std::vector<VmInstr> code;
   std::vector<double> imm;
   int64_t alg_bytes = 0;

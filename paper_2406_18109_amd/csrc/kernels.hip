@@ -101,7 +101,7 @@ int launch_vm(const VmParams& P, int is_f64, int tier, int rows, hipStream_t str
   const int nb = stream_bucket(P.n_in, tier);
   if (P.n_in > nb) return (int)hipErrorInvalidValue;
   switch (tier) {
-    case TIER_ARITH: return launch_vm_tier0(P, is_f64, nb, P.spmv ? 0 : rows, stream);
+    case TIER_ARITH: return launch_vm_tier0(P, is_f64, nb, (P.spmv || P.st_n > 0) ? 0 : rows, stream);
     case TIER_TRANS8: return launch_vm_tier1(P, is_f64, nb, stream);
     case TIER_TRANS16: return launch_vm_tier2(P, is_f64, nb, stream);
     default: return launch_vm_tier3(P, is_f64, nb, stream);

@@ -36,6 +36,14 @@ constexpr int BLOCK = 256;
 constexpr int VM_MAXTPW = 64;      // tiles per wave (power of two)
 constexpr int FINAL_CHUNK = 1024;  // tree level width processed in LDS (power of two)
 constexpr int FINAL_BLOCK = 1024;  // threads of the block-sum kernel (= FINAL_CHUNK)
+#ifndef DFX_ST_RCH
+#define DFX_ST_RCH 8
+#endif
+#ifndef DFX_ST_NBUF
+#define DFX_ST_NBUF 1
+#endif
+constexpr int ST_RCH = DFX_ST_RCH;   // output rows per stencil staging chunk (ST_RCH + 2 rows staged)
+constexpr int ST_NBUF = DFX_ST_NBUF; // staging buffers per wave (2: the next chunk loads during this one)
 
 template <typename T> struct Lanes;
 template <> struct Lanes<double> { static constexpr int V = 2, TW = WAVE * 2; };
@@ -125,6 +133,15 @@ struct VmParams {
   int32_t nnz;                     // length of colidx and val
   int64_t nx;                      // length of x
   int32_t sp_stage;                // stage each 64-row group's CSR range in LDS
+  int32_t sp_coop;                 // one-tile pass: the block's four waves compute its rows into LDS first
+  // Stencil staging (arithmetic 2-D passes): input streams that are shifted
+  // views of one store.  Element (row, col) of staged stream a is element
+  // (row + st_dr[a], col + st_dc[a]) of the window at st_base (row stride
+  // st_srow, st_lim elements readable from st_base).
+  int32_t st_n;                    // staged streams (0: none)
+  int8_t st_on[VM_MAXIN], st_dr[VM_MAXIN], st_dc[VM_MAXIN];
+  const void* st_base;
+  int64_t st_srow, st_lim;
   VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
 

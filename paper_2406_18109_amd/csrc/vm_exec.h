@@ -219,7 +219,11 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
 // SPMV_RT (with SPMV): the SpMV prologue runs only for passes that have one
 // (P.spmv), so one instantiation serves SpMV and elementwise passes alike
 // (the batched executor's).
-template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS, bool SPMV_RT = false>
+// STG: the step's staged streams (P.st_on) come from the wave's LDS slice
+// `stl` at chunk row q (vm_stencil_tile), the others from global memory;
+// MODE_FAST only.
+template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS, bool SPMV_RT = false,
+          bool STG = false>
 __device__ __forceinline__ void vm_step(
     const VmParams& P,
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
@@ -228,7 +232,7 @@ __device__ __forceinline__ void vm_step(
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R3)[NR],
     VmState<T, Shape<T, HV, SPMV, NR, ROWS>::NG, Shape<T, HV, SPMV, NR, ROWS>::GS>& G,
     T (&L)[NINB][Shape<T, HV, SPMV, NR, ROWS>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
-    const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval) {
+    const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval, const T* stl = nullptr, int q = 0) {
   typedef Shape<T, HV, SPMV, NR, ROWS> S;
   constexpr bool HEAVY = S::HEAVY;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
@@ -241,7 +245,29 @@ __device__ __forceinline__ void vm_step(
     else if (g_ == 2) gset<T, GS>(R2[a], (e) % GS, x); else gset<T, GS>(R3[a], (e) % GS, x); }
 
   // ---- loads ------------------------------------------------------------------
-  if (mode != MODE_SLOW && SPLIT) {
+  if constexpr (STG) {
+    constexpr int PITCH = TW + 16 / (int)sizeof(T);
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      if (a >= P.n_in) break;
+      if (P.st_on[a]) {
+        const T* src = stl + (q + P.st_dr[a]) * PITCH + lane * V + P.st_dc[a];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int v = 0; v < V; ++v) RSET(a, u * V + v, src[u * PITCH + v]);
+      } else {
+        const T* b = (const T*)P.in[a].base;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const vecA w = *(const vecA*)(b + (row0 + u) * P.in[a].s_row + c0);
+#pragma unroll
+          for (int v = 0; v < V; ++v) RSET(a, u * V + v, w[v]);
+        }
+      }
+    }
+  } else if (mode != MODE_SLOW && SPLIT) {
     // issued by the caller (or prefetched by the previous step) into L
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
@@ -300,7 +326,16 @@ __device__ __forceinline__ void vm_step(
     static_assert(U == 1, "SpMV steps take one row of the tiling");
     if (!SPMV_RT || P.spmv) {
       T y[4];
-      spmv_rows<T, V>(P, row0 * TW, y, scol, sval);
+      if (!SPMV_RT && P.sp_coop) {
+        // rows computed by the whole block before the tile (vm_kernel)
+        extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
+        const T* yt = (const T*)vm_dyn_lds;
+        const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+        for (int v = 0; v < V; ++v) y[v] = yt[row0 * TW + V * lane + v];
+      } else {
+        spmv_rows<T, V>(P, row0 * TW, y, scol, sval);
+      }
 #pragma unroll
       for (int e = 0; e < E; ++e) RSET(NR - 1, e, y[e]);
     }
@@ -490,12 +525,93 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
   return v;
 }
 
+// Stencil staging: an interior tile of a pass whose input streams include
+// shifted views of one store (the stencil of section 2: five offset views of
+// one grid).  The tile's rows are processed in chunks of ST_RCH; for each
+// chunk the wave loads the window's ST_RCH + 2 rows (TW + 2 columns) once,
+// with 16-byte loads all in flight together, into its LDS slice, and every
+// staged stream of every step then reads its shifted values from LDS
+// instead of fetching them again from L2.  Other streams load as usual.
+// The op list runs unchanged on the same values, so the bits are the same.
+constexpr int st_pitch(int tw, int es) { return tw + 16 / es; }
+
+template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS>
+__device__ __forceinline__ void vm_stencil_tile(
+    const VmParams& P, typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R1)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R2)[NR],
+    typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R3)[NR],
+    VmState<T, Shape<T, HV, SPMV, NR, ROWS>::NG, Shape<T, HV, SPMV, NR, ROWS>::GS>& G,
+    T (&L)[NINB][Shape<T, HV, SPMV, NR, ROWS>::E], int64_t tr, int64_t cbase, int64_t c0, int wib) {
+  typedef Shape<T, HV, SPMV, NR, ROWS> S;
+  constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E;
+  constexpr int PITCH = st_pitch(TW, (int)sizeof(T));
+  constexpr int SR = ST_RCH + 2;   // staged rows per chunk
+  static_assert(2 * SR <= 63, "outstanding staged loads fit the wait counter");
+  static_assert(ST_RCH % U == 0 && RED_TH % ST_RCH == 0, "stencil chunking");
+  extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
+  T* sl = (T*)vm_dyn_lds + (size_t)wib * ST_NBUF * SR * PITCH;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const T* gb = (const T*)P.st_base;
+  // stage chunk c (rows [tr * RED_TH + c * ST_RCH, + SR)) into buffer c % ST_NBUF
+  auto stage = [&](int c) {
+    const int64_t rb = tr * RED_TH + (int64_t)c * ST_RCH;
+    T* buf = sl + (size_t)(c % ST_NBUF) * SR * PITCH;
+#pragma unroll
+    for (int k = 0; k < SR; ++k) {
+      const T* rowp = gb + (rb + k) * P.st_srow + cbase;
+      __builtin_amdgcn_global_load_lds((const void*)(rowp + lane * V),
+                                       (__attribute__((address_space(3))) void*)(buf + k * PITCH), 16, 0, 0);
+      if (lane < 4)
+        __builtin_amdgcn_global_load_lds((const void*)((const char*)(rowp + TW) + lane * 4),
+                                         (__attribute__((address_space(3))) void*)(buf + k * PITCH + TW), 4, 0, 0);
+    }
+  };
+  constexpr int NCH = RED_TH / ST_RCH;
+  // direct global-to-LDS loads: each lane's 16 bytes of a row land at lane *
+  // 16 of the row's LDS line, the 16 halo bytes past the row by lanes 0..3;
+  // a chunk's rows are all in flight at once, holding no registers.  With
+  // two buffers the next chunk is staged while the current one is computed.
+  __builtin_amdgcn_s_waitcnt(0);   // earlier LDS reads of this slice are complete
+  stage(0);
+  for (int c = 0; c < NCH; ++c) {
+    if constexpr (ST_NBUF > 1) {
+      if (c + 1 < NCH) {
+        // the buffer chunk c + 1 overwrites was last read two chunks ago:
+        // wait for LDS reads only (lgkmcnt 0), then issue its loads
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        stage(c + 1);
+        // chunk c's loads are complete when at most chunk c + 1's 2 * SR
+        // loads (and nothing older) are outstanding: vmcnt(2 * SR)
+        __builtin_amdgcn_s_waitcnt(((2 * SR) & 0xF) | (((2 * SR) >> 4) << 14) | 0x70 | 0xF00);
+      } else {
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    const T* cur = sl + (size_t)(c % ST_NBUF) * SR * PITCH;
+    for (int q = 0; q < ST_RCH; q += U)
+      vm_step<T, HV, SPMV, NR, NINB, false, ROWS, false, true>(P, R0, R1, R2, R3, G, L,
+                                                               tr * RED_TH + (int64_t)c * ST_RCH + q, c0,
+                                                               (1u << E) - 1, MODE_FAST, false, 0, nullptr, nullptr,
+                                                               cur, q);
+    if constexpr (ST_NBUF == 1)
+      if (c + 1 < NCH) {
+        __builtin_amdgcn_s_waitcnt(0);
+        stage(c + 1);
+      }
+  }
+}
+
 // SpMV passes keep four waves per SIMD (one tile per wave fills the chip
 // only if all of them are resident)
 #ifndef DFX_SPMV_WAVES
 #define DFX_SPMV_WAVES 4
 #endif
-template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS>
+// STEN: the stencil-staging variant of the arithmetic kernel (a separate
+// instantiation, so the other kernels keep their registers).
+template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS, bool STEN = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SPMV && HV == 0 ? DFX_SPMV_WAVES : 1)))
 void vm_kernel(const VmParams P) {
   typedef Shape<T, HV, SPMV, NR, ROWS> S;
@@ -505,6 +621,40 @@ void vm_kernel(const VmParams P) {
   // SpMV kernels: per wave, the staged CSR range of one 64-row group
   __shared__ int32_t sp_col[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
   __shared__ T sp_val[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
+
+  // One-tile SpMV passes (sp_coop, one block): the block's four waves first
+  // compute the tile's rows, four 64-row groups per lane at once, into
+  // dynamic LDS; the wave that owns the tile then reads them there.  Each
+  // row is summed in CSR order as always, so the bits do not change.
+  if constexpr (SPMV) {
+    if (P.sp_coop) {
+      extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
+      T* yt = (T*)vm_dyn_lds;
+      const int lane_ = threadIdx.x & (WAVE - 1);
+      const int w_ = threadIdx.x / WAVE;
+      constexpr int GPW = TW * RED_TH / WAVE / (BLOCK / WAVE);   // 64-row groups per wave
+      const uint32_t nx = (uint32_t)P.nx;
+#ifndef DFX_COOP_ROWS
+#define DFX_COOP_ROWS 2
+#endif
+      constexpr int CR = DFX_COOP_ROWS;   // rows walked at once per lane
+      for (int k0 = 0; k0 < GPW; k0 += CR) {
+        int64_t ii[CR];
+        bool ok[CR];
+        T yy[CR];
+#pragma unroll
+        for (int m = 0; m < CR; ++m) {
+          ii[m] = (int64_t)(w_ * GPW + k0 + m) * WAVE + lane_;
+          ok[m] = ii[m] < P.n1d;
+        }
+        csr_rows<T, CR>(P.rowptr, P.colidx, (const T*)P.val, (const T*)P.x, ii, ok, P.nnz, nx, yy);
+#pragma unroll
+        for (int m = 0; m < CR; ++m)
+          if (ok[m]) yt[ii[m]] = yy[m];
+      }
+      __syncthreads();
+    }
+  }
 
   gvec R0[NR], R1[NR], R2[NR], R3[NR];  // groups beyond NG are unused (and dropped)
   VmState<T, NG, GS> G;
@@ -565,7 +715,15 @@ void vm_kernel(const VmParams P) {
     const int64_t c0 = cbase + (int64_t)lane * V;
     G.acc0 = G.acc1 = G.acc2 = G.acc3 = (T)0;
     bool have = false;  // L already holds this step's values (prefetched)
-    for (int r = 0; r < RED_TH; r += U) {
+    bool staged = false;
+    if constexpr (STEN && !SPMV && HV == 0) {
+      // stencil passes: a whole interior tile whose staged window lies in
+      // the store goes through LDS (vm_stencil_tile)
+      staged = P.st_n > 0 && P.unit_cols && (tr + 1) * RED_TH <= P.rows && cbase + TW <= P.cols &&
+               ((tr + 1) * RED_TH + 1) * P.st_srow + cbase + TW + 16 / (int)sizeof(T) <= P.st_lim;
+      if (staged) vm_stencil_tile<T, HV, SPMV, NR, NINB, ROWS>(P, R0, R1, R2, R3, G, L, tr, cbase, c0, wib);
+    }
+    for (int r = 0; r < (staged ? 0 : RED_TH); r += U) {
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= P.rows) break;
       const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
@@ -623,15 +781,32 @@ template <int HV, int NR, int NB0, int NB1, int NB2, int ROWS = 0>
 int launch_tier(const VmParams& P, int is_f64, int nb, hipStream_t st) {
   const dim3 g(P.grid), b(BLOCK);
   const bool sp = P.spmv != 0;
-#define DFX_L(T, SP)                                                                              \
-  {                                                                                               \
-    if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0, ROWS>), g, b, 0, st, P);     \
-    else if (nb == NB1) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB1, ROWS>), g, b, 0, st, P); \
-    else hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB2, ROWS>), g, b, 0, st, P);               \
+  // one-tile SpMV passes stage the tile's rows in dynamic LDS (same bytes
+  // for FP64 and FP32: RED_TH rows of 16 bytes per lane)
+  // stencil passes: per wave ST_RCH + 2 staged rows of TW elements and 16
+  // more bytes (the halo columns)
+  const bool sten = HV == 0 && ROWS == 0 && !sp && P.st_n > 0 && nb != NB0;
+  const size_t dyn = sp && P.sp_coop ? (size_t)RED_TH * WAVE * 16
+                     : sten          ? (size_t)(BLOCK / WAVE) * ST_NBUF * (ST_RCH + 2) * (WAVE * 16 + 16)
+                                     : 0;
+#define DFX_L(T, SP)                                                                                \
+  {                                                                                                 \
+    if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0, ROWS>), g, b, dyn, st, P);     \
+    else if (nb == NB1) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB1, ROWS>), g, b, dyn, st, P); \
+    else hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB2, ROWS>), g, b, dyn, st, P);               \
   }
   if constexpr (ROWS > 0) {
     if (sp) return (int)hipErrorInvalidValue;   // SpMV steps take one row in every variant
     if (is_f64) DFX_L(double, false) else DFX_L(float, false)
+  } else if (sten) {
+    // stencil staging (three or more staged streams: the wider buckets)
+    if (is_f64) {
+      if (nb == NB1) hipLaunchKernelGGL((vm_kernel<double, HV, false, NR, NB1, 0, true>), g, b, dyn, st, P);
+      else hipLaunchKernelGGL((vm_kernel<double, HV, false, NR, NB2, 0, true>), g, b, dyn, st, P);
+    } else {
+      if (nb == NB1) hipLaunchKernelGGL((vm_kernel<float, HV, false, NR, NB1, 0, true>), g, b, dyn, st, P);
+      else hipLaunchKernelGGL((vm_kernel<float, HV, false, NR, NB2, 0, true>), g, b, dyn, st, P);
+    }
   } else {
     if (is_f64) {
       if (sp) DFX_L(double, true) else DFX_L(double, false)
