@@ -18,8 +18,9 @@
 
 namespace dfx {
 
-int launch_batch(const BatchPass* passes, BatchStream* streams, BatchCtl* ctl, int grid, hipStream_t stream);
-int batch_waves_per_cu();
+int launch_batch(const BatchPass* passes, BatchStream* streams, BatchCtl* ctl, int grid, int heavy,
+                 hipStream_t stream);
+int batch_waves_per_cu(int heavy);
 
 struct BatchRec {
   dfx_batch* b = nullptr;
@@ -39,6 +40,7 @@ struct dfx_batch {
   int device = 0;
   hipStream_t stream = nullptr;
   std::vector<BatchPass> passes;
+  std::vector<char> pass_heavy;       // the pass needs the transcendental op set
   std::vector<BatchStream> streams;   // host copy: tables, and the state read back by dfx_batch_wait
   std::vector<int64_t> max_tiles;     // per stream
   BatchCtl ctl{};
@@ -51,6 +53,7 @@ struct dfx_batch {
   bool started = false;
   bool pending = false;   // a launch not yet waited for
   int grid = 0;
+  int grid_hv[2] = {0, 0};   // resident blocks of the arithmetic / transcendental kernel
   int n_xcd = 1;          // XCDs (L2 domains) of the device; stream s runs on XCD s % n_xcd
   std::string err;
 };
@@ -91,6 +94,7 @@ int batch_record_pass(Ctx& c, const VmParams& P, const VmFinal& F, int dtype, in
     B.result[k] = F.result[k];
   }
   r->b->passes.push_back(B);
+  r->b->pass_heavy.push_back(tier == TIER_TRANS8 ? 1 : 0);
   return DFX_OK;
 }
 
@@ -100,6 +104,7 @@ void batch_record_drop(Ctx& c) {
   c.batch_rec = nullptr;
   if (!r) return;
   r->b->passes.resize(r->pass0);
+  r->b->pass_heavy.resize(r->pass0);
   r->b->recording -= 1;
   delete r;
 }
@@ -120,11 +125,12 @@ int dfx_batch_create(int32_t device, void* stream, dfx_batch** out) {
     delete b;
     return DFX_EHIP;
   }
-  const int w = batch_waves_per_cu();
   // every block resident; gfx950 has 32 compute units per XCD, and blocks
   // are dispatched to the XCDs in turn, so each XCD gets grid / n_xcd of them
   b->n_xcd = std::max(1, std::min(BATCH_MAX_XCD, n_cu / 32));
-  b->grid = std::max(b->n_xcd, n_cu * std::max(w, 4) / (BLOCK / WAVE));
+  for (int h = 0; h < 2; ++h)
+    b->grid_hv[h] = std::max(b->n_xcd, n_cu * std::max(batch_waves_per_cu(h), 4) / (BLOCK / WAVE));
+  b->grid = b->grid_hv[1];
   *out = b;
   return DFX_OK;
 }
@@ -196,6 +202,7 @@ int dfx_batch_record_end(dfx_batch* b, dfx_ctx* c, int32_t max_iter, dfx_store c
   b->recording -= 1;
   if (rc != DFX_OK || r->rc != DFX_OK) {
     b->passes.resize(r->pass0);   // drop what this stream recorded
+    b->pass_heavy.resize(r->pass0);
     const std::string m = rc != DFX_OK ? std::string("flush: ") + dfx_last_error(c) : r->err;
     const int e = rc != DFX_OK ? rc : r->rc;
     delete r;
@@ -297,7 +304,9 @@ int dfx_batch_run(dfx_batch* b, int32_t round_limit, int32_t restart) {
       hipMemcpy(b->d_ctl, &b->ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) != hipSuccess)
     return bfail(b, DFX_EHIP, "batch state upload");
   if (settled == ns) return DFX_OK;
-  const int e = launch_batch(b->d_passes, b->d_streams, b->d_ctl, b->grid, b->stream);
+  const int heavy = std::find(b->pass_heavy.begin(), b->pass_heavy.end(), 1) != b->pass_heavy.end() ? 1 : 0;
+  b->grid = b->grid_hv[heavy];
+  const int e = launch_batch(b->d_passes, b->d_streams, b->d_ctl, b->grid, heavy, b->stream);
   if (e != 0) return bfail(b, DFX_EHIP, std::string("batch launch: ") + hipGetErrorString((hipError_t)e));
   b->pending = true;
   return DFX_OK;

@@ -21,13 +21,12 @@ namespace dfx {
 
 namespace {
 
-// One instantiation serves every pass of a batch: FP64, the transcendental
-// op set with 8 registers, up to 6 input streams, the SpMV prologue taken
-// when the pass has one, one row per step.
+// One instantiation serves every pass of a batch: FP64, 8 registers, up to
+// 6 input streams, the SpMV prologue taken when the pass has one, one row
+// per step; with the transcendental op set (HV 1) when any pass needs it,
+// else the arithmetic one (HV 0, fewer registers).
 typedef double BT;
-constexpr int BHV = 1, BNR = VM_NREG_LIGHT, BNINB = 6;
-typedef Shape<BT, BHV, true, BNR, 0> BS;
-typedef GVec<BT, BS::GS>::type bgvec;
+constexpr int BNR = VM_NREG_LIGHT, BNINB = 6;
 
 // Synchronisation.  Streams are pinned to XCDs, so every wave that reads a
 // stream's data runs on the XCD whose L2 holds it.  A run's stores are
@@ -102,7 +101,10 @@ __device__ double wave_tree(const double* a, int64_t n, double* scratch, int lan
 }
 
 // Execute run r of pass B for stream st: tiles [r * tpw, min(n_tiles, (r+1) * tpw)).
+template <int BHV>
 __device__ void run_tiles(const BatchPass& B, const BatchStream& st, int64_t r, int32_t* scol, double* sval) {
+  typedef Shape<BT, BHV, true, BNR, 0> BS;
+  typedef typename GVec<BT, BS::GS>::type bgvec;
   const VmParams& P = B.P;
   constexpr int V = BS::V, U = BS::U, TW = BS::TW, E = BS::E;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -163,6 +165,7 @@ __device__ void run_tiles(const BatchPass& B, const BatchStream& st, int64_t r, 
 #define DFX_BATCH_STALL_TICKS 200000000ull
 #endif
 
+template <int BHV>
 __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restrict__ passes,
                                                      BatchStream* __restrict__ streams, BatchCtl* __restrict__ ctl) {
   __shared__ int32_t sp_col[BLOCK / WAVE][SP_CAP];
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
       acq_sid = sid;
       acq_gen = gen;
     }
-    run_tiles(B, st, run, sp_col[wib], sp_val[wib]);
+    run_tiles<BHV>(B, st, run, sp_col[wib], sp_val[wib]);
     since = __builtin_amdgcn_s_memrealtime();
     // release every lane's stores of this run, then count it
     xcd_release();
@@ -326,16 +329,19 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchPass* __restric
 
 }  // namespace
 
-// Waves one compute unit holds of the batch kernel.
-int batch_waves_per_cu() {
+// Waves one compute unit holds of the batch kernel (heavy: the
+// transcendental variant).
+int batch_waves_per_cu(int heavy) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void*)&batch_kernel, BLOCK, 0) != hipSuccess)
-    return 0;
+  const void* f = heavy ? (const void*)&batch_kernel<1> : (const void*)&batch_kernel<0>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, BLOCK, 0) != hipSuccess) return 0;
   return blocks * (BLOCK / WAVE);
 }
 
-int launch_batch(const BatchPass* passes, BatchStream* streams, BatchCtl* ctl, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(BLOCK), 0, stream, passes, streams, ctl);
+int launch_batch(const BatchPass* passes, BatchStream* streams, BatchCtl* ctl, int grid, int heavy,
+                 hipStream_t stream) {
+  if (heavy) hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(BLOCK), 0, stream, passes, streams, ctl);
+  else hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(BLOCK), 0, stream, passes, streams, ctl);
   return (int)hipGetLastError();
 }
 

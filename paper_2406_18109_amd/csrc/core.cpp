@@ -621,6 +621,10 @@ struct SInstr {
   int a = -1, b = -1, dst = -1;   // value ids
   int imm = 0, slot = 0;
   bool dead = false;
+  bool operator==(const SInstr& o) const {
+    return op == o.op && a == o.a && b == o.b && dst == o.dst && imm == o.imm && slot == o.slot;
+  }
+  bool operator!=(const SInstr& o) const { return !(*this == o); }
 };
 
 struct Lowering {
@@ -700,6 +704,41 @@ static void set_shape(PassPlan& p, int64_t tpw) {
   int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
   if (grid > 8) grid = (grid + 7) / 8 * 8;
   p.grid = (int)grid;
+}
+
+// Reorder a pass's instructions so that a value is consumed right after it
+// is produced whenever a consumer is ready: that consumer takes it from the
+// accumulator (no register write-back for a single use, no operand fetch)
+// and may merge with it into one dispatch.  Any topological order of the
+// value graph computes the same bits (every op rounds on its own; each
+// reduction has its own slot), so the choice is free; otherwise the
+// original order is kept.
+static void schedule_chain(std::vector<SInstr>& code, size_t n_vals) {
+  const int n = (int)code.size();
+  std::vector<int> prod(n_vals, -1);
+  for (int i = 0; i < n; ++i)
+    if (code[i].dst >= 0) prod[code[i].dst] = i;
+  std::vector<char> done(n, 0);
+  auto ready = [&](int i) {
+    for (int v : {code[i].a, code[i].b})
+      if (v >= 0 && prod[v] >= 0 && !done[prod[v]]) return false;
+    return true;
+  };
+  std::vector<SInstr> out;
+  out.reserve(n);
+  int prev = -1;
+  for (int k = 0; k < n; ++k) {
+    int pick = -1;
+    if (prev >= 0)
+      for (int i = 0; i < n && pick < 0; ++i)
+        if (!done[i] && (code[i].a == prev || code[i].b == prev) && ready(i)) pick = i;
+    for (int i = 0; i < n && pick < 0; ++i)
+      if (!done[i] && ready(i)) pick = i;
+    done[pick] = 1;
+    out.push_back(code[pick]);
+    prev = code[pick].dst;
+  }
+  code.swap(out);
 }
 
 static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& tasks, const Space& sp,
@@ -849,27 +888,32 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   for (auto& I : code)
     if (!I.dead) kept.push_back(I);
   code.swap(kept);
-  for (size_t i = 0; i < code.size(); ++i)
-    if (code[i].dst >= 0) vals[code[i].dst].idx = (int)i;
-  // operand uses
+  const std::vector<SInstr> program_order = code;
+  schedule_chain(code, vals.size());
+  // definitions, operand uses, last uses and write-backs of the current order
   const int INF = 1 << 30;
-  std::vector<std::vector<int>> uses(vals.size());
-  for (size_t i = 0; i < code.size(); ++i) {
-    if (code[i].a >= 0) uses[code[i].a].push_back((int)i);
-    if (code[i].b >= 0 && code[i].b != code[i].a) uses[code[i].b].push_back((int)i);
-  }
-  for (size_t v = 0; v < vals.size(); ++v) {
-    int lu = -1;
-    for (int u : uses[v]) lu = std::max(lu, u);
-    if (vals[v].stored) lu = INF;
-    vals[v].last_use = lu;
-    if (vals[v].kind == 2) {
-      const int d = vals[v].idx;
-      bool only_next = !vals[v].stored && !uses[v].empty();
-      for (int u : uses[v]) only_next = only_next && u == d + 1;
-      vals[v].wb = !only_next;
+  auto analyse = [&]() {
+    for (size_t i = 0; i < code.size(); ++i)
+      if (code[i].dst >= 0) vals[code[i].dst].idx = (int)i;
+    std::vector<std::vector<int>> uses(vals.size());
+    for (size_t i = 0; i < code.size(); ++i) {
+      if (code[i].a >= 0) uses[code[i].a].push_back((int)i);
+      if (code[i].b >= 0 && code[i].b != code[i].a) uses[code[i].b].push_back((int)i);
     }
-  }
+    for (size_t v = 0; v < vals.size(); ++v) {
+      int lu = -1;
+      for (int u : uses[v]) lu = std::max(lu, u);
+      if (vals[v].stored) lu = INF;
+      vals[v].last_use = lu;
+      if (vals[v].kind == 2) {
+        const int d = vals[v].idx;
+        bool only_next = !vals[v].stored && !uses[v].empty();
+        for (int u : uses[v]) only_next = only_next && u == d + 1;
+        vals[v].wb = !only_next;
+      }
+    }
+  };
+  analyse();
   // unused inputs are still loaded (their stream is bound); unused
   // broadcasts are dropped from the register file but keep their slot
   if (out.ins.size() > (size_t)VM_MAXIN || out.bc_cstore.size() > (size_t)VM_MAXBC ||
@@ -925,6 +969,20 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     return true;
   };
   const int nin = (int)out.ins.size();
+  // keep the chained order only if it fits the register file the program
+  // order fits
+  if (!has_pow && nin <= 6 && code != program_order) {
+    const int b8 = stream_bucket(nin, heavy ? TIER_TRANS8 : TIER_ARITH);
+    if (!allocate(VM_NREG_LIGHT, b8)) {
+      const std::vector<SInstr> chained = code;
+      code = program_order;
+      analyse();
+      if (!allocate(VM_NREG_LIGHT, b8)) {
+        code = chained;
+        analyse();
+      }
+    }
+  }
   bool ok = false;
   if (!has_pow && nin <= 6) {
     tier = heavy ? TIER_TRANS8 : TIER_ARITH;
@@ -951,14 +1009,20 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
     const bool binary = I.op == VO_ADD || I.op == VO_SUB || I.op == VO_MUL || I.op == VO_DIV ||
                         I.op == VO_MAX || I.op == VO_MIN || I.op == VO_REDPROD || I.op == VO_POW;
     // IEEE addition and multiplication are commutative bit for bit: put the
-    // forwarded operand first so it stays in the accumulator
+    // forwarded operand first so it stays in the accumulator.  A forwarded
+    // right operand of a subtraction or division stays in the accumulator
+    // through the reversed op (b - a and b / a are the same IEEE operations).
     if (binary && (I.op == VO_ADD || I.op == VO_MUL || I.op == VO_REDPROD) && I.b == prev && I.a != prev)
       std::swap(I.a, I.b);
+    else if ((I.op == VO_SUB || I.op == VO_DIV) && I.b == prev && I.a != prev) {
+      I.op = I.op == VO_SUB ? VO_RSUB : VO_RDIV;
+      std::swap(I.a, I.b);
+    }
     if (I.a >= 0) {
       if (I.a == prev) flags |= VF_A_ACC;
       else { ra = (unsigned)vals[I.a].reg; flags |= VF_A_REG; }
     }
-    if (binary && I.b >= 0) {
+    if ((binary || I.op == VO_RSUB || I.op == VO_RDIV) && I.b >= 0) {
       if (I.b == prev) flags |= VF_B_ACC;
       else { rb = (unsigned)vals[I.b].reg; flags |= VF_B_REG; }
     }
@@ -976,7 +1040,7 @@ static int lower_pass(Ctx& c, Lowering& L, const std::vector<const TaskRec*>& ta
   // op from register c), when at most one of the two uses the immediate
   auto post_ok = [](unsigned op) {
     return op == VO_NEG || op == VO_SQUARE || op == VO_ADDI || op == VO_SUBI || op == VO_RSUBI ||
-           op == VO_MULI || op == VO_ADD || op == VO_SUB || op == VO_MUL;
+           op == VO_MULI || op == VO_ADD || op == VO_SUB || op == VO_MUL || op == VO_RSUB;
   };
   std::vector<EI> merged;
   for (size_t i = 0; i < em.size(); ++i) {

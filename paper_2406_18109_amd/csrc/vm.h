@@ -51,6 +51,7 @@ template <> struct Lanes<float> { static constexpr int V = 4, TW = WAVE * 4; };
 
 enum VmOp : uint8_t {
   VO_MOV = 0, VO_NEG, VO_ABS, VO_SQUARE, VO_ADD, VO_SUB, VO_MUL, VO_DIV, VO_MAX, VO_MIN,
+  VO_RSUB, VO_RDIV,   // b - a, b / a: the accumulator as the right operand
   VO_ADDI, VO_SUBI, VO_RSUBI, VO_MULI, VO_DIVI, VO_RDIVI, VO_FILL,
   VO_RED, VO_REDPROD,
   // ops below need the transcendental kernel variant

@@ -398,6 +398,8 @@ __device__ __forceinline__ void vm_step(
       case VO_DIV: VEC(X(g) / y[g])
       case VO_MAX: BIN(d_max<T>)
       case VO_MIN: BIN(d_min<T>)
+      case VO_RSUB: VEC(y[g] - X(g))
+      case VO_RDIV: VEC(y[g] / X(g))
       case VO_ADDI: VEC(X(g) + k)
       case VO_SUBI: VEC(X(g) - k)
       case VO_RSUBI: VEC(k - X(g))
@@ -452,6 +454,7 @@ __device__ __forceinline__ void vm_step(
         case VO_ADD: VEC(X(g) + y[g])
         case VO_SUB: VEC(X(g) - y[g])
         case VO_MUL: VEC(X(g) * y[g])
+        case VO_RSUB: VEC(y[g] - X(g))
         case VO_ADDI: VEC(X(g) + k)
         case VO_SUBI: VEC(X(g) - k)
         case VO_RSUBI: VEC(k - X(g))
