@@ -30,6 +30,20 @@ HBM_PEAK_GBS = 8000.0
 # --tune: contexts time launch-shape candidates on each plan's first
 # executions (then every leg warms up for at least 8 executions)
 TUNE = False
+# compiled passes: 1 = background compilation (the default), 0 = every pass
+# interpreted.  Legs wait for the compiler before their timed region and
+# report its time (compile_s) apart from the first iteration.
+JIT = 1
+
+
+def jit_settle(dfx, step):
+    """Wait for queued kernel compilation, then run one more untimed step so
+    every compiled kernel is loaded before timing; returns the compile
+    seconds spent so far in this process."""
+    if JIT:
+        dfx.jit_wait()
+        step()
+    return dfx.jit_info()["compile_seconds"] if JIT else 0.0
 
 
 def log(*a):
@@ -42,7 +56,8 @@ def kernel_source_hash():
               "paper_2406_18109_amd/csrc/vm_exec.h", "paper_2406_18109_amd/csrc/dev_common.h",
               "paper_2406_18109_amd/csrc/vm_tier0.hip", "paper_2406_18109_amd/csrc/vm_tier1.hip",
               "paper_2406_18109_amd/csrc/vm_tier2.hip", "paper_2406_18109_amd/csrc/vm_tier3.hip",
-              "paper_2406_18109_amd/csrc/dmath.h", "paper_2406_18109_amd/csrc/dmath_coef.h"):
+              "paper_2406_18109_amd/csrc/dmath.h", "paper_2406_18109_amd/csrc/dmath_coef.h",
+              "paper_2406_18109_amd/csrc/vm_instr.inc", "paper_2406_18109_amd/csrc/jit.cpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -113,7 +128,7 @@ class BSBench:
     def __init__(self, dfx, synth, np, n, dtype, fuse):
         self.np = np
         npdt = np.float64 if dtype == "f64" else np.float32
-        self.ctx = dfx.Context(device=0, window_size=64, fuse=fuse, tune=TUNE)
+        self.ctx = dfx.Context(device=0, window_size=64, fuse=fuse, tune=TUNE, jit=JIT)
         self.dfx, self.n, self.dtype = dfx, n, dtype
         S, K, T = synth.bs_inputs(n, npdt)
         c = self.ctx
@@ -174,6 +189,8 @@ def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W, runs=0):
     analysis = b.ctx.stats()["analysis_seconds"]
     for _ in range(max(W, 8) if TUNE else W):
         b.step()
+    c0 = dfx.jit_info()["compile_seconds"]
+    compile_s = jit_settle(dfx, b.step) - c0 if JIT else 0.0
     b.ctx.stats_reset()
     wall, ev = timed_steps(torch, b.ctx.torch_stream, b.step, K)
     st = b.ctx.stats()
@@ -188,14 +205,16 @@ def bs_leg(torch, dfx, synth, np, n, dtype, fuse, K, W, runs=0):
            "launches_per_step": launches, "gbs": bytes_per_step / (wall * 1e-3) / 1e9,
            "kernel_gbs": bytes_per_step / (ev_ms * 1e-3) / 1e9, "first_pass_ms": first * 1e3,
            "analysis_s": analysis, "tasks_per_pass": st["tasks_dispatched"] / K,
-           "groups_per_pass": st["groups_dispatched"] / K}
+           "groups_per_pass": st["groups_dispatched"] / K, "jit": JIT, "compile_s": compile_s,
+           "compiled_launches_per_pass": st["compiled_launches"] / K}
     if paper is not None:
         out["paper_method_ms_per_step"] = paper
     return out
 
 
 def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
-    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE, jit=JIT)
+    c0 = dfx.jit_info()["compile_seconds"]
     G = c.store_create([N, N], "f64")
     c.store_write(G, synth.jacobi_grid(N))
     J = dfx.apps.Jacobi(c, G, N)
@@ -206,6 +225,7 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
     first = time.perf_counter() - t0
     for _ in range(8 if TUNE else 2):
         J.sweep()
+    compile_s = jit_settle(dfx, J.sweep) - c0 if JIT else 0.0
     c.sync()
     c.stats_reset()
     torch.cuda.synchronize()
@@ -217,7 +237,8 @@ def jacobi_leg(torch, dfx, synth, np, N, sweeps, fuse):
     st = c.stats()
     out = {"sweeps": sweeps, "ms_per_sweep": dt * 1e3, "alg_bytes_per_sweep": st["alg_bytes"] / sweeps,
            "gbs": st["alg_bytes"] / sweeps / dt / 1e9, "launches_per_sweep": st["launches"] / sweeps,
-           "first_sweep_ms": first * 1e3}
+           "first_sweep_ms": first * 1e3, "jit": JIT, "compile_s": compile_s,
+           "compiled_launches_per_sweep": st["compiled_launches"] / sweeps}
     out.update(counts(st, sweeps))
     c.close()
     return out
@@ -228,7 +249,8 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg", runs=
     nonsymmetric convection-diffusion matrix of the same shape.  With
     `runs`, the timed region is repeated that many times and the paper's
     method (drop fastest and slowest, mean of the rest) gives ms_per_iter."""
-    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE, jit=JIT)
+    c0 = dfx.jit_info()["compile_seconds"]
     if solver == "cg":
         rowptr, col, val = synth.poisson_csr(m, dim)
         seed = synth.CG64_SEED if dim == 2 else synth.CG256_SEED
@@ -254,6 +276,7 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg", runs=
     analysis = c.stats()["analysis_seconds"]
     for _ in range(8 if TUNE else 1):
         cg.iteration()
+    compile_s = jit_settle(dfx, cg.iteration) - c0 if JIT else 0.0
     c.sync()
     g = None
     capture = None
@@ -281,7 +304,8 @@ def cg_leg(torch, dfx, synth, np, m, dim, iters, fuse, graph, solver="cg", runs=
     st = c.stats()
     out = {"iters": iters, "iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
            "alg_bytes_per_iter": st["alg_bytes"] / iters,
-           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3, "analysis_s": analysis}
+           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3, "analysis_s": analysis,
+           "jit": JIT, "compile_s": compile_s, "compiled_launches_per_iter": st["compiled_launches"] / iters}
     out.update(counts(st, iters))
     if capture is not None:
         out["capture_ms"] = capture * 1e3
@@ -306,7 +330,8 @@ def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph, runs=0):
     """The GMG solver (CG preconditioned by one V(2,2) cycle, injection
     restriction, weighted Jacobi) on the m^2 Poisson problem over nlev
     levels; with graph, one whole iteration is recorded and replayed."""
-    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE)
+    c = dfx.Context(device=0, window_size=16, fuse=fuse, tune=TUNE, jit=JIT)
+    c0 = dfx.jit_info()["compile_seconds"]
     levels = synth.gmg_levels(m, nlev)
 
     def up(a):
@@ -323,6 +348,7 @@ def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph, runs=0):
     g.iteration()
     c.sync()
     first = time.perf_counter() - t0
+    compile_s = jit_settle(dfx, g.iteration) - c0 if JIT else 0.0
     gid = None
     capture = None
     if graph:
@@ -349,7 +375,8 @@ def gmg_leg(torch, dfx, synth, np, m, nlev, iters, fuse, graph, runs=0):
     st = c.stats()
     out = {"iters": iters, "iters_per_s": 1.0 / dt, "ms_per_iter": dt * 1e3,
            "alg_bytes_per_iter": st["alg_bytes"] / iters,
-           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3}
+           "gbs": st["alg_bytes"] / iters / dt / 1e9, "first_iter_ms": first * 1e3,
+           "jit": JIT, "compile_s": compile_s, "compiled_launches_per_iter": st["compiled_launches"] / iters}
     out.update(counts(st, iters))
     if capture is not None:
         out["capture_ms"] = capture * 1e3
@@ -377,10 +404,17 @@ def breakeven(fused, unfused, key_ms, first_key):
     f_ss, u_ss = fused[key_ms], unfused[key_ms]
     extra = (fused[first_key] + fused.get("capture_ms", 0.0) - f_ss) - (unfused[first_key] - u_ss)
     gain = u_ss - f_ss
-    return {"one_time_ms_fused": fused[first_key] + fused.get("capture_ms", 0.0) - f_ss,
-            "one_time_ms_unfused": unfused[first_key] - u_ss,
-            "gain_ms_per_iter": gain,
-            "breakeven_iters": (max(0.0, extra) / gain) if gain > 0 else None}
+    out = {"one_time_ms_fused": fused[first_key] + fused.get("capture_ms", 0.0) - f_ss,
+           "one_time_ms_unfused": unfused[first_key] - u_ss,
+           "gain_ms_per_iter": gain,
+           "breakeven_iters": (max(0.0, extra) / gain) if gain > 0 else None}
+    # kernel compilation runs on a host thread while the passes run
+    # interpreted; counted as one-time cost it moves the breakeven to
+    cf, cu = fused.get("compile_s", 0.0) * 1e3, unfused.get("compile_s", 0.0) * 1e3
+    if cf or cu:
+        out["compile_ms_fused"], out["compile_ms_unfused"] = cf, cu
+        out["breakeven_iters_with_compile"] = (max(0.0, extra + cf - cu) / gain) if gain > 0 else None
+    return out
 
 
 def serve_leg(dfx, synth, np, count, rate, budget, slots, ipr=0, mats=None):
@@ -696,11 +730,14 @@ def main():
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--jacobi-sweeps", type=int, default=200, help="fused Jacobi sweeps timed (the config's 200)")
     ap.add_argument("--cg256-iters", type=int, default=500, help="CG 256^3 iterations timed (the config's 500)")
+    ap.add_argument("--jit", type=int, default=1, choices=[0, 1],
+                    help="1: passes compiled in the background (timed once ready); 0: interpreted")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timings on the host")
     ap.add_argument("--quick-cpu", action="store_true", help="small oracle samples (a smoke run of the bench)")
     args = ap.parse_args()
-    global TUNE
+    global TUNE, JIT
     TUNE = args.tune
+    JIT = args.jit
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the executor runs on "
               "a single device)" % args.gpus, file=sys.stderr)
@@ -830,7 +867,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "black-scholes fused pass, 2^%d options FP64 (28 index tasks -> 1 kernel)" % args.log2n,
-                   "options": n, "tasks_per_pass": 28, "parallelism": "1 GPU"},
+                   "options": n, "tasks_per_pass": 28, "parallelism": "1 GPU",
+                   "kernel": "compiled pass (hiprtc, op list as constants)" if JIT else "op-list interpreter"},
         "roofline": roof,
         "legs": legs,
     }

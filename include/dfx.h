@@ -121,7 +121,15 @@ typedef struct {
                             up to auto_window (>= window_size, else EINVAL), and the tasks
                             stay buffered.  Once a full window does not fuse as a whole, the
                             size stays.  Flushes are not affected.  Needs fuse = 1. */
-  int32_t reserved[7];
+  int32_t jit;           /* compiled passes (section 6's JIT code generation): 0 off, every
+                            pass interpreted.  1: a pass's first execution queues its kernel
+                            for compilation on a background thread; it runs interpreted until
+                            the kernel is ready, then compiled.  2: the first execution
+                            compiles it in the caller.  Needs memo = 1 (else EINVAL).  A
+                            compiled pass returns the same bits as the interpreted one.
+                            The environment variable DFX_JIT=1 or 2 sets it for contexts
+                            created with jit = 0 and memo = 1. */
+  int32_t reserved[6];
 } dfx_config;
 
 typedef struct {
@@ -152,6 +160,7 @@ typedef struct {
   int64_t graph_replays;
   int64_t alg_bytes;             /* algorithmic HBM bytes of everything launched */
   double analysis_seconds;       /* host time in analysis + lowering (misses only) */
+  int64_t compiled_launches;     /* pass launches that ran a compiled kernel */
 } dfx_stats;
 
 #define DFX_INFO_MAX 64
@@ -268,6 +277,41 @@ int dfx_stats_reset(dfx_ctx* ctx);
  * be one that dfx_plan_cache_save wrote. */
 int dfx_plan_cache_save(dfx_ctx* ctx, const char* path, int64_t* n_saved);
 int dfx_plan_cache_load(dfx_ctx* ctx, const char* path, int64_t* n_loaded);
+/* ---- compiled passes (jit = 1 or 2) ----------------------------------- */
+/* Section 6 generates and JIT-compiles a kernel per fused task.  Here a
+ * memoised pass's op list is written out as the body of the op-list kernel
+ * template (one call per instruction, its fields as constants) and compiled
+ * with hiprtc for gfx950; tiling, loads, stores and the reduction tree are
+ * the template's, so the bits do not change.  Kernels are shared by every
+ * context of the process (keyed by their instantiation and source text) and, when a cache
+ * directory is set (dfx_jit_cache_dir or the DFX_JIT_CACHE environment
+ * variable), stored there as code objects and reused by later processes.
+ * A kernel that fails to compile or load leaves its pass interpreted.
+ * Which passes run compiled (measured on MI355X): those with transcendental
+ * ops, those of fewer than 256 tiles (latency-bound) and stencil-staged ones;
+ * large arithmetic and SpMV passes stream as fast interpreted and stay so.
+ * DFX_JIT_ALL=1 compiles every pass. */
+typedef struct {
+  int64_t compiled;              /* kernels compiled by this process */
+  int64_t failed;                /* kernels that failed to compile */
+  int64_t disk_hits;             /* kernels read from the cache directory */
+  int32_t pending;               /* queued or compiling */
+  int32_t reserved;
+  double compile_seconds;        /* time spent compiling (disk hits excluded) */
+} dfx_jit_info;
+/* Blocks until no compilation is queued or running (process-wide). */
+int dfx_jit_wait(void);
+int dfx_jit_info_get(dfx_jit_info* out);
+/* Directory for code objects ("" or NULL: no disk cache).  The directory
+ * must exist; files are named by a hash of the kernel source, the embedded
+ * headers, the compile options and the hiprtc version. */
+int dfx_jit_cache_dir(const char* dir);
+/* Compiles, in the caller, the kernel of every pass of every memoised plan
+ * of the context that would run compiled and has none yet (also in an
+ * analysis-only context, which compiles without loading); *n_failed counts
+ * those that failed. */
+int dfx_jit_precompile(dfx_ctx* ctx, int64_t* n_failed);
+
 /* Current window size: window_size, or what automatic sizing has grown it to. */
 int dfx_window_size(dfx_ctx* ctx, int32_t* out);
 /* Number of groups recorded since the last reset, and the i-th one. */

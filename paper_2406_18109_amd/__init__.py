@@ -6,5 +6,5 @@ host and hand-written gfx950 HIP kernels on the device.  `_binding` is the
 ctypes layer with the C-ABI's names; `apps` issues the workloads' task
 streams through it.
 """
-from ._binding import Batch, Context, DfxError, lib  # noqa: F401
+from ._binding import Batch, Context, DfxError, jit_cache_dir, jit_info, jit_wait, lib  # noqa: F401
 from . import apps  # noqa: F401

@@ -43,7 +43,7 @@ class dfx_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
                 ("dealloc", FREE_FN), ("alloc_user", C.c_void_p), ("window_size", C.c_int32),
                 ("fuse", C.c_int32), ("memo", C.c_int32), ("tune", C.c_int32), ("auto_window", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("jit", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class dfx_arg(C.Structure):
@@ -61,7 +61,13 @@ class dfx_stats(C.Structure):
                 ("groups_dispatched", C.c_int64), ("launches", C.c_int64),
                 ("temporaries_eliminated", C.c_int64), ("memo_hits", C.c_int64),
                 ("memo_misses", C.c_int64), ("graph_replays", C.c_int64),
-                ("alg_bytes", C.c_int64), ("analysis_seconds", C.c_double)]
+                ("alg_bytes", C.c_int64), ("analysis_seconds", C.c_double),
+                ("compiled_launches", C.c_int64)]
+
+
+class dfx_jit_info(C.Structure):
+    _fields_ = [("compiled", C.c_int64), ("failed", C.c_int64), ("disk_hits", C.c_int64),
+                ("pending", C.c_int32), ("reserved", C.c_int32), ("compile_seconds", C.c_double)]
 
 
 class dfx_group_info(C.Structure):
@@ -124,6 +130,10 @@ SIGNATURES = {
     "dfx_stats_get": (C.c_int, [C.c_void_p, C.POINTER(dfx_stats)]),
     "dfx_stats_reset": (C.c_int, [C.c_void_p]),
     "dfx_window_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "dfx_jit_wait": (C.c_int, []),
+    "dfx_jit_info_get": (C.c_int, [C.POINTER(dfx_jit_info)]),
+    "dfx_jit_cache_dir": (C.c_int, [C.c_char_p]),
+    "dfx_jit_precompile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "dfx_plan_cache_save": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "dfx_plan_cache_load": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "dfx_group_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -165,6 +175,24 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+def jit_wait():
+    """Block until no pass kernel is queued or compiling (process-wide)."""
+    lib().dfx_jit_wait()
+
+
+def jit_info() -> dict:
+    s = dfx_jit_info()
+    rc = lib().dfx_jit_info_get(C.byref(s))
+    if rc != 0:
+        raise DfxError(rc, "dfx_jit_info_get failed")
+    return {k: getattr(s, k) for k, _ in dfx_jit_info._fields_ if k != "reserved"}
+
+
+def jit_cache_dir(path):
+    """Directory of compiled code objects shared across processes (None: off)."""
+    lib().dfx_jit_cache_dir(os.fsencode(path) if path else None)
 
 
 class DfxError(RuntimeError):
@@ -213,7 +241,7 @@ class Context:
     """One dfx context (dfx_create ... dfx_destroy)."""
 
     def __init__(self, device: int = 0, window_size: int = 16, fuse: bool = True, memo: bool = True,
-                 stream=None, allocator: str = "torch", tune: bool = False, auto_window: int = 0):
+                 stream=None, allocator: str = "torch", tune: bool = False, auto_window: int = 0, jit: int = 0):
         self.L = lib()
         cfg = dfx_config()
         cfg.device = device
@@ -222,6 +250,7 @@ class Context:
         cfg.memo = 1 if memo else 0
         cfg.tune = 1 if tune else 0
         cfg.auto_window = auto_window
+        cfg.jit = int(jit)
         self._alloc = None
         self.torch_stream = None
         if device >= 0:
@@ -436,6 +465,12 @@ class Context:
     def plan_cache_load(self, path) -> int:
         n = C.c_int64()
         self._chk(self.L.dfx_plan_cache_load(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
+
+    def jit_precompile(self) -> int:
+        """Compile every memoised pass's kernel now; returns how many failed."""
+        n = C.c_int64()
+        self._chk(self.L.dfx_jit_precompile(self.h, C.byref(n)))
         return n.value
 
     def window_size(self) -> int:

@@ -1275,6 +1275,56 @@ static bool stencil_enabled() {
   return on;
 }
 
+// A reducing pass whose tiles all belong to block 0 (one block sum) writes
+// its 0-d results from that block; not when recorded into a batch (the
+// batched executor reduces tile sums itself).  DFX_RED_DIRECT=0 turns it off.
+static bool red_direct(const Ctx& c, const PassPlan& p) {
+  static const bool on = [] {
+    const char* e = std::getenv("DFX_RED_DIRECT");
+    return !(e && e[0] == '0');
+  }();
+  return on && !c.batch_rec && p.n_tiles >= 1 && p.n_tiles <= 4 * p.tiles_per_wave;
+}
+
+// Passes that run compiled when jit is on (measured on MI355X):
+// transcendental passes, where the interpreter's dispatch dominates
+// (Black-Scholes FP64 over 2^26 options: 0.79 against 1.05 ms); small
+// passes of fewer than 256 tiles, which are latency-bound (CG 64^2: 0.074
+// against 0.100 ms per iteration); stencil-staged passes (the 8192^2 Jacobi
+// sweep: 0.46 against 0.51 ms).  Large arithmetic and staged-SpMV passes
+// stream at the interpreter's rate or slightly below it compiled (the CG
+// 256^3 SpMV + dot: 438 against 390 us) and stay interpreted.
+// DFX_JIT_ALL=1 compiles every pass.
+static bool jit_wanted(const PassPlan& p, int st_n) {
+  const char* all = std::getenv("DFX_JIT_ALL");
+  if (all && all[0] == '1') return true;
+  return p.tier != TIER_ARITH || p.n_tiles < 256 || st_n > 0;
+}
+
+// The pass's program and kernel variant for compilation (rows: the rows per
+// step the interpreter would take).
+static std::shared_ptr<JitEntry> request_compiled(PassPlan& p, int st_n, int rows, bool sync) {
+  JitProgram g;
+  g.code = p.code;
+  g.out_reg = p.out_reg;
+  g.bc_reg = p.bc_reg;
+  const JitVariant v = jit_variant(p.dtype == DFX_F64, p.tier, (int)p.ins.size(), p.kind == 1, st_n, rows);
+  std::string name;
+  const std::string src = jit_source(v, g, &name);
+  return jit_request(src, name, sync);
+}
+
+// Staged streams of a pass when it runs (stencil staging on and the plan's
+// views recorded).
+static int staged_streams(const PassPlan& p, size_t n_stores) {
+  if (!(p.st_cs >= 0 && (size_t)p.st_cs < n_stores && stencil_enabled() && p.st_on.size() == p.ins.size() &&
+        p.st_dr.size() == p.ins.size() && p.st_dc.size() == p.ins.size()))
+    return 0;
+  int n = 0;
+  for (int8_t o : p.st_on) n += o;
+  return n;
+}
+
 static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   auto S = [&](int cs) -> StoreRec& { return c.stores.at(order[cs]); };
   const size_t es = dtype_size(p.dtype);
@@ -1295,12 +1345,18 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   } else if (!c.no_alloc && !c.batch_rec && (rc = ensure_workspace(c, p))) {
     return rc;
   }
-  // the pass, plus the block-sum kernel when it reduces
-  const int n_launch = p.red_cstore.empty() ? 1 : 2;
-  c.stats.launches += n_launch;
-  c.stats.alg_bytes += p.alg_bytes;
-  if (c.capturing) { c.capture_launches += n_launch; c.capture_bytes += p.alg_bytes; }
-  if (c.analysis_only) return DFX_OK;
+  // the pass, plus the block-sum kernel when it reduces over more than one
+  // block (counted once the launch shape is final)
+  auto count_launches = [&]() {
+    const int n_launch = p.red_cstore.empty() || red_direct(c, p) ? 1 : 2;
+    c.stats.launches += n_launch;
+    c.stats.alg_bytes += p.alg_bytes;
+    if (c.capturing) { c.capture_launches += n_launch; c.capture_bytes += p.alg_bytes; }
+  };
+  if (c.analysis_only) {
+    count_launches();
+    return DFX_OK;
+  }
 
   // Launch-shape tuner.  A memoised pass runs once untimed (warm-up), then
   // each candidate twice, interleaved, between two events; a timing is read
@@ -1342,6 +1398,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     }
   }
 
+  count_launches();
   VmParams P;
   std::memset(&P, 0, sizeof(P));
   P.n_code = (int)p.code.size();
@@ -1397,7 +1454,10 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     F.partials[k] = P.red_partials[k];
     F.result[k] = S(p.red_cstore[k]).ptr;
     F.init[k] = p.red_init[k];
+    P.red_result[k] = F.result[k];
+    P.red_init[k] = F.init[k];
   }
+  P.red_direct = P.n_red > 0 && red_direct(c, p) ? 1 : 0;
   if (p.kind == 1) {
     P.rowptr = (const int32_t*)S(p.spmv_rowptr).ptr;
     P.colidx = (const int32_t*)S(p.spmv_col).ptr;
@@ -1418,8 +1478,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   }
   for (size_t i = 0; i < p.code.size(); ++i) P.code[i] = p.code[i];
   P.st_n = 0;
-  if (p.st_cs >= 0 && p.st_cs < (int)order.size() && stencil_enabled() && p.st_on.size() == p.ins.size() && p.st_dr.size() == p.ins.size() &&
-      p.st_dc.size() == p.ins.size()) {
+  if (staged_streams(p, order.size()) > 0) {
     const StoreRec& ss = S(p.st_cs);
     for (size_t a = 0; a < p.ins.size(); ++a) {
       P.st_on[a] = p.st_on[a];
@@ -1432,9 +1491,29 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.st_lim = ss.elems - p.st_off0;
   }
   if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
+  const int rows = pick_rows(c, p);
+  // compiled kernel, once ready (module loading is kept out of captures)
+  hipFunction_t fn = nullptr;
+  if (c.cfg.jit) {
+    if (!p.jit_checked) {
+      p.jit_checked = true;
+      if (jit_wanted(p, P.st_n)) p.jit = request_compiled(p, P.st_n, rows, c.cfg.jit == 2);
+    }
+    if (p.jit) fn = jit_function(*p.jit, c.cfg.device, !c.capturing);
+  }
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
-  int e = launch_vm(P, p.dtype == DFX_F64, p.tier, pick_rows(c, p), c.stream);
-  if (e == 0 && F.n_red > 0) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
+  int e;
+  if (fn) {
+    const JitVariant v = jit_variant(p.dtype == DFX_F64, p.tier, P.n_in, P.spmv, P.st_n, rows);
+    void* args[] = {(void*)&P};
+    e = (int)hipModuleLaunchKernel(fn, (unsigned)P.grid, 1, 1, BLOCK, 1, 1, (unsigned)vm_dyn_lds_bytes(P, v.sten != 0),
+                                   c.stream, args, nullptr);
+    c.stats.compiled_launches += 1;
+    if (c.capturing) c.capture_compiled += 1;
+  } else {
+    e = launch_vm(P, p.dtype == DFX_F64, p.tier, rows, c.stream);
+  }
+  if (e == 0 && F.n_red > 0 && !P.red_direct) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
   if (timed) (void)hipEventRecord(p.ev1, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
@@ -1658,8 +1737,13 @@ int dfx_create(const dfx_config* cfg, dfx_ctx** out) {
   if (cfg->window_size < 1) return DFX_EINVAL;
   if (cfg->auto_window < 0 || (cfg->auto_window > 0 && (cfg->auto_window < cfg->window_size || !cfg->fuse)))
     return DFX_EINVAL;
+  if (cfg->jit < 0 || cfg->jit > 2 || (cfg->jit && !cfg->memo)) return DFX_EINVAL;
   dfx_ctx* c = new dfx_ctx();
   c->cfg = *cfg;
+  // DFX_JIT=1|2 turns compiled passes on for contexts created with jit = 0
+  // (runs an unchanged program on compiled kernels)
+  if (const char* j = std::getenv("DFX_JIT"))
+    if (!c->cfg.jit && c->cfg.memo && (j[0] == '1' || j[0] == '2') && !j[1]) c->cfg.jit = j[0] - '0';
   c->window_cur = cfg->window_size;
   c->stream = (hipStream_t)cfg->stream;
   c->analysis_only = cfg->device < 0;
@@ -2014,6 +2098,7 @@ int dfx_graph_begin(dfx_ctx* c) {
   c->capturing = true;
   c->capture_launches = 0;
   c->capture_bytes = 0;
+  c->capture_compiled = 0;
   return DFX_OK;
 }
 
@@ -2032,6 +2117,7 @@ int dfx_graph_end(dfx_ctx* c, int32_t* graph_id) {
   if (e != hipSuccess) { (void)hipGraphDestroy(g); return fail(*c, DFX_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
   G->launches = c->capture_launches;
   G->alg_bytes = c->capture_bytes;
+  G->compiled = c->capture_compiled;
   c->graphs.push_back(std::move(G));
   *graph_id = (int32_t)c->graphs.size() - 1;
   return DFX_OK;
@@ -2046,6 +2132,7 @@ int dfx_graph_launch(dfx_ctx* c, int32_t id) {
   c->stats.graph_replays += 1;
   c->stats.launches += c->graphs[id]->launches;
   c->stats.alg_bytes += c->graphs[id]->alg_bytes;
+  c->stats.compiled_launches += c->graphs[id]->compiled;
   return DFX_OK;
 }
 
@@ -2056,6 +2143,46 @@ int dfx_graph_destroy(dfx_ctx* c, int32_t id) {
   (void)hipGraphExecDestroy(c->graphs[id]->exec);
   (void)hipGraphDestroy(c->graphs[id]->graph);
   c->graphs[id].reset();
+  return DFX_OK;
+}
+
+int dfx_jit_wait(void) {
+  jit_wait_idle();
+  return DFX_OK;
+}
+
+int dfx_jit_info_get(dfx_jit_info* out) {
+  if (!out) return DFX_EINVAL;
+  const JitCounters n = jit_counters();
+  std::memset(out, 0, sizeof(*out));
+  out->compiled = n.compiled;
+  out->failed = n.failed;
+  out->disk_hits = n.disk_hits;
+  out->pending = n.pending;
+  out->compile_seconds = n.seconds;
+  return DFX_OK;
+}
+
+int dfx_jit_cache_dir(const char* dir) {
+  jit_set_cache_dir(dir ? dir : "");
+  return DFX_OK;
+}
+
+int dfx_jit_precompile(dfx_ctx* c, int64_t* n_failed) {
+  if (!c) return DFX_EINVAL;
+  int64_t failed = 0;
+  for (auto& kv : c->memo) {
+    for (auto& p : kv.second->passes) {
+      const int rows = c->analysis_only ? 0 : pick_rows(*c, p);
+      const int st_n = staged_streams(p, SIZE_MAX);
+      if (!p.jit && !jit_wanted(p, st_n)) continue;
+      if (!p.jit) p.jit = request_compiled(p, st_n, rows, true);
+      p.jit_checked = true;
+      if (jit_state(*p.jit) == 0) jit_wait_idle();
+      if (jit_state(*p.jit) < 0) failed += 1;
+    }
+  }
+  if (n_failed) *n_failed = failed;
   return DFX_OK;
 }
 

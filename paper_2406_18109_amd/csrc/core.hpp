@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/dfx.h"
+#include "jit.h"
 #include "vm.h"
 
 namespace dfx {
@@ -125,6 +126,10 @@ struct PassPlan {
   int tune_step = 0;          // execution count while tuning (0: the untimed warm-up)
   int tune_pending = -1;      // candidate whose events are in flight
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // compiled kernel of this pass (jit = 1 or 2): requested at the first
+  // execution, shared by every plan with the same program and variant
+  std::shared_ptr<JitEntry> jit;
+  bool jit_checked = false;   // whether the pass runs compiled is decided
 };
 
 struct Plan {
@@ -139,6 +144,7 @@ struct Graph {
   hipGraphExec_t exec = nullptr;
   int64_t launches = 0;
   int64_t alg_bytes = 0;
+  int64_t compiled = 0;   // launches of compiled kernels in the graph
 };
 
 struct Ctx {
@@ -163,7 +169,7 @@ struct Ctx {
   std::vector<dfx_group_info> groups;
 
   bool capturing = false;
-  int64_t capture_launches = 0, capture_bytes = 0;
+  int64_t capture_launches = 0, capture_bytes = 0, capture_compiled = 0;
   std::vector<std::unique_ptr<Graph>> graphs;
 
   dfx_stats stats{};

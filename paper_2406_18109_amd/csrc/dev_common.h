@@ -1,7 +1,9 @@
 // Device helpers shared by the op-list kernel and the batched CG kernels:
 // the fixed reduction trees that make every sum independent of launch shape.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "vm.h"
 

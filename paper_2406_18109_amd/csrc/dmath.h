@@ -5,7 +5,9 @@
 // from gen_dmath.py.  Measured against the host C library they stay
 // within a few ulp over the whole double range.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "dmath_coef.h"
 

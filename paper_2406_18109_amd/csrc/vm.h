@@ -3,6 +3,9 @@
 // argument block.
 #pragma once
 #include <stdint.h>
+#ifndef __HIPCC_RTC__
+#include <stddef.h>
+#endif
 
 namespace dfx {
 
@@ -127,6 +130,14 @@ struct VmParams {
   int32_t bc_reg[VM_MAXBC];
   const void* bc[VM_MAXBC];
   void* red_partials[VM_MAXRED];   // one subtree sum per block
+  // red_direct: the pass's tiles form one block's subtree (one block
+  // reduces), so that block's sum is the whole tree's: the block writes the
+  // 0-d result itself (red_result[k] = red_init[k] ? sum : red_result[k] +
+  // sum, the block-sum kernel's arithmetic for one block sum) and no
+  // block-sum kernel follows
+  int32_t red_direct;
+  int32_t red_init[VM_MAXRED];
+  void* red_result[VM_MAXRED];
   const int32_t* rowptr;           // SpMV operands (n1d + 1 row pointers)
   const int32_t* colidx;
   const void* val;
@@ -145,6 +156,16 @@ struct VmParams {
   int64_t st_srow, st_lim;
   VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
+
+// Dynamic LDS bytes of a pass's launch: a one-tile SpMV pass stages the
+// tile's rows (RED_TH rows of 16 bytes per lane, FP64 and FP32 alike); a
+// stencil-staged pass gives each wave ST_NBUF buffers of ST_RCH + 2 rows of
+// TW elements plus 16 bytes of halo.
+inline size_t vm_dyn_lds_bytes(const VmParams& P, bool sten) {
+  return P.spmv && P.sp_coop ? (size_t)RED_TH * WAVE * 16
+         : sten              ? (size_t)(BLOCK / WAVE) * ST_NBUF * (ST_RCH + 2) * (WAVE * 16 + 16)
+                             : 0;
+}
 
 // Allocation-free execution (dfx_flush_noalloc): the block sums of a pass's
 // reductions go to a fixed device array of NOALLOC_BLOCKS sums per reduction

@@ -12,8 +12,10 @@
 // in LDS and a one-block kernel launched after the pass combines the block
 // sums.  The kernel templates are instantiated per tier in their own sources.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <math.h>
+#endif
 #include <stdint.h>
 
 #include "dev_common.h"
@@ -137,6 +139,40 @@ template <typename T, int NG, int GS> struct VmState {
   T acc0, acc1, acc2, acc3; // this lane's reduction accumulators
 };
 
+// One instruction of the op list over every element slot of a step, for
+// compiled passes: their generated program calls it once per instruction
+// with the fields as constants, so the op switch folds away and every
+// register index is a constant (the register file becomes plain VGPRs).
+// The interpreter executes the same body (vm_instr.inc) with the fields it
+// decodes at run time, so both forms round alike.
+template <typename T, int HV, int NR, int NG, int GS, int E>
+__device__ __forceinline__ void vm_instr(typename GVec<T, GS>::type (&R0)[NR], typename GVec<T, GS>::type (&R1)[NR],
+                                         typename GVec<T, GS>::type (&R2)[NR], typename GVec<T, GS>::type (&R3)[NR],
+                                         VmState<T, NG, GS>& G, const unsigned vmask, const unsigned op,
+                                         const unsigned flags, const unsigned slot, const unsigned post,
+                                         const unsigned d, const unsigned ia, const unsigned ib, const unsigned ic,
+                                         const T k) {
+  constexpr bool HEAVY = HV > 0;
+  typedef typename GVec<T, GS>::type gvec;
+#include "vm_instr.inc"
+}
+
+// The op list a kernel executes.  VmInterp interprets the pass's code
+// (P.code, P.out_reg, P.bc_reg).  A compiled pass's program type, generated
+// by the host for that one pass, has COMPILED true, its output and
+// broadcast register maps as constants, its waves-per-SIMD target (WAVES)
+// and a run() that calls vm_instr for each instruction in order.
+struct VmInterp {
+  static constexpr bool COMPILED = false;
+  static constexpr int WAVES = 1;
+  static constexpr int out_reg[VM_MAXOUT] = {};
+  static constexpr int bc_reg[VM_MAXBC] = {};
+  template <typename T, int HV, int NR, int NG, int GS, int E>
+  static __device__ __forceinline__ void run(typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
+                                             typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
+                                             VmState<T, NG, GS>&, unsigned) {}
+};
+
 enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
 
 // y = A x for the V*64 elements of a step starting at element `base`.  The
@@ -223,7 +259,7 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
 // `stl` at chunk row q (vm_stencil_tile), the others from global memory;
 // MODE_FAST only.
 template <typename T, int HV, bool SPMV, int NR, int NINB, bool SPLIT, int ROWS, bool SPMV_RT = false,
-          bool STG = false>
+          bool STG = false, class PG = VmInterp>
 __device__ __forceinline__ void vm_step(
     const VmParams& P,
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
@@ -308,19 +344,40 @@ __device__ __forceinline__ void vm_step(
 #pragma unroll
       for (int e = 0; e < E; ++e) RSET(a, e, Ls[a][e]);
   } else {
-    for (int a = 0; a < P.n_in; ++a) {
-      const T* b = (const T*)P.in[a].base;
-      const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;
-      gvec w[NG];
+    // per-element masked loads, one stream at a time (a compiled pass
+    // unrolls the streams, so its register indices stay constants)
+#define DFX_SLOW_LOAD(a)                                                 \
+  {                                                                      \
+    const T* b = (const T*)P.in[a].base;                                 \
+    const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;                \
+    gvec w[NG];                                                          \
+    _Pragma("unroll") for (int e = 0; e < E; ++e) {                      \
+      const int u = e / V, v = e % V;                                    \
+      const bool ok = (vmask >> e) & 1;                                  \
+      const T q = b[ok ? (row0 + u) * sr + (c0 + v) * sc : 0];           \
+      gset<T, GS>(w[e / GS], e % GS, ok ? q : (T)0);                     \
+    }                                                                    \
+    FOR_G(Rg[a] = w[g];)                                                 \
+  }
+    if constexpr (PG::COMPILED) {
+      // unrolled over the streams (constant register indices); the row and
+      // column pass through an empty asm so that the per-element addresses
+      // of this rare path are formed here, not kept live across the tile's
+      // row loop by strength reduction
+      int64_t row0x = row0, c0x = c0;
+      asm volatile("" : "+s"(row0x), "+v"(c0x));
+      {
+        const int64_t row0 = row0x, c0 = c0x;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int u = e / V, v = e % V;
-        const bool ok = (vmask >> e) & 1;
-        const T q = b[ok ? (row0 + u) * sr + (c0 + v) * sc : 0];
-        gset<T, GS>(w[e / GS], e % GS, ok ? q : (T)0);
+        for (int a = 0; a < NINB; ++a) {
+          if (a >= P.n_in) break;
+          DFX_SLOW_LOAD(a)
+        }
       }
-      FOR_G(Rg[a] = w[g];)
+    } else {
+      for (int a = 0; a < P.n_in; ++a) DFX_SLOW_LOAD(a)
     }
+#undef DFX_SLOW_LOAD
   }
   if constexpr (SPMV) {
     static_assert(U == 1, "SpMV steps take one row of the tiling");
@@ -342,6 +399,9 @@ __device__ __forceinline__ void vm_step(
   }
 
   // ---- op list: the next instruction's load overlaps the current op --------
+  if constexpr (PG::COMPILED) {
+    PG::template run<T, HV, NR, NG, GS, E>(R0, R1, R2, R3, G, vmask);
+  } else {
   VmInstr nx = P.code[0];
   for (int pc = 0; pc < P.n_code; ++pc) {
     const unsigned w0 = __builtin_amdgcn_readfirstlane(nx.w0), w1 = __builtin_amdgcn_readfirstlane(nx.w1);
@@ -353,121 +413,8 @@ __device__ __forceinline__ void vm_step(
     T k;
     if constexpr (sizeof(T) == 8) k = __builtin_bit_cast(double, ((uint64_t)w3 << 32) | w2);
     else k = __builtin_bit_cast(float, w2);
-    // Accumulator machine: G.z holds the previous result and becomes this
-    // instruction's result in place.  Operand a is the accumulator unless it
-    // comes from a register (indexed read straight into G.z); operand b is
-    // fetched only by binary ops, and is the previous result only when the
-    // planner could not make it operand a.
-    gvec y[NG];
-    if (flags & VF_B_ACC) {
-#pragma unroll
-      for (int g = 0; g < NG; ++g) y[g] = G.z[g];
-    } else if (flags & VF_B_REG) {
-      FOR_G(y[g] = Rg[ib];)
-    }
-    if (flags & VF_A_REG) FOR_G(G.z[g] = Rg[ia];)
-#define X(g) G.z[g]
-#define VEC(EXPR) { _Pragma("unroll") for (int g = 0; g < NG; ++g) G.z[g] = EXPR; } break;
-#define UN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS))); } break;
-// FP64: all E elements through the lockstep form of the function at once
-#define UNW(FN, F)                                                                                 \
-  {                                                                                                \
-    if constexpr (sizeof(T) == 8) {                                                                \
-      constexpr int EH = E / DFX_MATH_SPLIT;                                                       \
-      _Pragma("unroll") for (int h = 0; h < DFX_MATH_SPLIT; ++h) {                                 \
-        double a_[EH];                                                                             \
-        _Pragma("unroll") for (int e = 0; e < EH; ++e) a_[e] = gget<T, GS>(G.z[(h * EH + e) / GS], (h * EH + e) % GS); \
-        FN(a_);                                                                                    \
-        _Pragma("unroll") for (int e = 0; e < EH; ++e) gset<T, GS>(G.z[(h * EH + e) / GS], (h * EH + e) % GS, (T)a_[e]); \
-      }                                                                                            \
-    } else {                                                                                       \
-      _Pragma("unroll") for (int e = 0; e < E; ++e)                                                \
-        gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS)));                    \
-    }                                                                                              \
-  }                                                                                                \
-  break;
-#define BIN(F) { _Pragma("unroll") for (int e = 0; e < E; ++e) gset<T, GS>(G.z[e / GS], e % GS, F(gget<T, GS>(G.z[e / GS], e % GS), gget<T, GS>(y[e / GS], e % GS))); } break;
-    switch (op) {
-      case VO_MOV: break;
-      case VO_NEG: VEC(-X(g))
-      case VO_ABS: UN(d_abs<T>)
-      case VO_SQUARE: VEC(X(g) * X(g))
-      case VO_ADD: VEC(X(g) + y[g])
-      case VO_SUB: VEC(X(g) - y[g])
-      case VO_MUL: VEC(X(g) * y[g])
-      case VO_DIV: VEC(X(g) / y[g])
-      case VO_MAX: BIN(d_max<T>)
-      case VO_MIN: BIN(d_min<T>)
-      case VO_RSUB: VEC(y[g] - X(g))
-      case VO_RDIV: VEC(y[g] / X(g))
-      case VO_ADDI: VEC(X(g) + k)
-      case VO_SUBI: VEC(X(g) - k)
-      case VO_RSUBI: VEC(k - X(g))
-      case VO_MULI: VEC(X(g) * k)
-      case VO_DIVI: VEC(X(g) / k)
-      case VO_RDIVI: VEC(k / X(g))
-      case VO_FILL: VEC((gvec)k)
-      case VO_RED:
-      case VO_REDPROD: {
-        // sequential over the slots in canonical order, valid slots only; the
-        // accumulator keeps operand a
-        T s = slot == 0 ? G.acc0 : slot == 1 ? G.acc1 : slot == 2 ? G.acc2 : G.acc3;
-        if (op == VO_REDPROD) {
-#pragma unroll
-          for (int e = 0; e < E; ++e)
-            if ((vmask >> e) & 1) s = s + gget<T, GS>(X(e / GS), e % GS) * gget<T, GS>(y[e / GS], e % GS);
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e)
-            if ((vmask >> e) & 1) s = s + gget<T, GS>(X(e / GS), e % GS);
-        }
-        switch (slot) {
-          case 0: G.acc0 = s; break;
-          case 1: G.acc1 = s; break;
-          case 2: G.acc2 = s; break;
-          default: G.acc3 = s; break;
-        }
-      } break;
-      default:
-        if constexpr (HEAVY) {
-          switch (op) {
-            case VO_SQRT: UN(d_sqrt<T>)
-            case VO_EXP: UNW(dm_exp, d_exp<T>)
-            case VO_LOG: UNW(dm_log, d_log<T>)
-            case VO_ERF: UNW(dm_erf, d_erf<T>)
-            case VO_POW:
-              if constexpr (HV >= 2) {
-                BIN(d_pow<T>)
-              }
-              break;
-            default: break;
-          }
-        }
-        break;
-    }
-    // superinstruction: a cheap follow-up op on the accumulator
-    if (post != 0) {
-      if (flags & VF_C_REG) FOR_G(y[g] = Rg[ic];)
-      switch (post - 1) {
-        case VO_NEG: VEC(-X(g))
-        case VO_SQUARE: VEC(X(g) * X(g))
-        case VO_ADD: VEC(X(g) + y[g])
-        case VO_SUB: VEC(X(g) - y[g])
-        case VO_MUL: VEC(X(g) * y[g])
-        case VO_RSUB: VEC(y[g] - X(g))
-        case VO_ADDI: VEC(X(g) + k)
-        case VO_SUBI: VEC(X(g) - k)
-        case VO_RSUBI: VEC(k - X(g))
-        case VO_MULI: VEC(X(g) * k)
-        default: break;
-      }
-    }
-#undef X
-#undef VEC
-#undef BIN
-#undef UN
-#undef UNW
-    if (flags & VF_WB) FOR_G(Rg[d] = G.z[g];)
+#include "vm_instr.inc"
+  }
   }
 
   // ---- stores -----------------------------------------------------------------
@@ -475,7 +422,7 @@ __device__ __forceinline__ void vm_step(
 #pragma unroll
     for (int s = 0; s < VM_MAXOUT; ++s) {
       if (s < P.n_out) {
-        const int o = P.out_reg[s];
+        const int o = PG::COMPILED ? PG::out_reg[s] : P.out_reg[s];
         gvec ev[NG];
         FOR_G(ev[g] = Rg[o];)
         T* b = (T*)P.out[s].base;
@@ -491,18 +438,36 @@ __device__ __forceinline__ void vm_step(
       }
     }
   } else {
-    for (int s = 0; s < P.n_out; ++s) {
-      const int o = P.out_reg[s];
-      gvec ev[NG];
-      FOR_G(ev[g] = Rg[o];)
-      T* b = (T*)P.out[s].base;
-      const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;
+#define DFX_SLOW_STORE(s, o)                                                                   \
+  {                                                                                            \
+    gvec ev[NG];                                                                               \
+    FOR_G(ev[g] = Rg[o];)                                                                      \
+    T* b = (T*)P.out[s].base;                                                                  \
+    const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;                                    \
+    _Pragma("unroll") for (int q = 0; q < E; ++q) {                                            \
+      const int u = q / V, v = q % V;                                                          \
+      if ((vmask >> q) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = gget<T, GS>(ev[q / GS], q % GS); \
+    }                                                                                          \
+  }
+    if constexpr (PG::COMPILED) {
+      // as the slow loads: unrolled, addresses formed here
+      int64_t row0x = row0, c0x = c0;
+      asm volatile("" : "+s"(row0x), "+v"(c0x));
+      {
+        const int64_t row0 = row0x, c0 = c0x;
 #pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const int u = q / V, v = q % V;
-        if ((vmask >> q) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = gget<T, GS>(ev[q / GS], q % GS);
+        for (int s = 0; s < VM_MAXOUT; ++s) {
+          if (s >= P.n_out) break;
+          DFX_SLOW_STORE(s, PG::out_reg[s])
+        }
+      }
+    } else {
+      for (int s = 0; s < P.n_out; ++s) {
+        const int o = P.out_reg[s];
+        DFX_SLOW_STORE(s, o)
       }
     }
+#undef DFX_SLOW_STORE
   }
 #undef RSET
 }
@@ -538,7 +503,7 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
 // The op list runs unchanged on the same values, so the bits are the same.
 constexpr int st_pitch(int tw, int es) { return tw + 16 / es; }
 
-template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS>
+template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS, class PG>
 __device__ __forceinline__ void vm_stencil_tile(
     const VmParams& P, typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R0)[NR],
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R1)[NR],
@@ -595,7 +560,7 @@ __device__ __forceinline__ void vm_stencil_tile(
     }
     const T* cur = sl + (size_t)(c % ST_NBUF) * SR * PITCH;
     for (int q = 0; q < ST_RCH; q += U)
-      vm_step<T, HV, SPMV, NR, NINB, false, ROWS, false, true>(P, R0, R1, R2, R3, G, L,
+      vm_step<T, HV, SPMV, NR, NINB, false, ROWS, false, true, PG>(P, R0, R1, R2, R3, G, L,
                                                                tr * RED_TH + (int64_t)c * ST_RCH + q, c0,
                                                                (1u << E) - 1, MODE_FAST, false, 0, nullptr, nullptr,
                                                                cur, q);
@@ -614,8 +579,10 @@ __device__ __forceinline__ void vm_stencil_tile(
 #endif
 // STEN: the stencil-staging variant of the arithmetic kernel (a separate
 // instantiation, so the other kernels keep their registers).
-template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS, bool STEN = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SPMV && HV == 0 ? DFX_SPMV_WAVES : 1)))
+// A compiled pass states its own waves-per-SIMD target (PG::WAVES).
+template <typename T, int HV, bool SPMV, int NR, int NINB, int ROWS, bool STEN = false, class PG = VmInterp>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(PG::COMPILED ? PG::WAVES : SPMV && HV == 0 ? DFX_SPMV_WAVES : 1)))
 void vm_kernel(const VmParams P) {
   typedef Shape<T, HV, SPMV, NR, ROWS> S;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
@@ -665,7 +632,7 @@ void vm_kernel(const VmParams P) {
   for (int k = 0; k < VM_MAXBC; ++k) {
     if (k < P.n_bc) {
       const gvec v = (gvec)(*(const T*)P.bc[k]);
-      const int r = P.bc_reg[k];
+      const int r = PG::COMPILED ? PG::bc_reg[k] : P.bc_reg[k];
       FOR_G(Rg[r] = v;)
     }
   }
@@ -724,7 +691,7 @@ void vm_kernel(const VmParams P) {
       // the store goes through LDS (vm_stencil_tile)
       staged = P.st_n > 0 && P.unit_cols && (tr + 1) * RED_TH <= P.rows && cbase + TW <= P.cols &&
                ((tr + 1) * RED_TH + 1) * P.st_srow + cbase + TW + 16 / (int)sizeof(T) <= P.st_lim;
-      if (staged) vm_stencil_tile<T, HV, SPMV, NR, NINB, ROWS>(P, R0, R1, R2, R3, G, L, tr, cbase, c0, wib);
+      if (staged) vm_stencil_tile<T, HV, SPMV, NR, NINB, ROWS, PG>(P, R0, R1, R2, R3, G, L, tr, cbase, c0, wib);
     }
     for (int r = 0; r < (staged ? 0 : RED_TH); r += U) {
       const int64_t row0 = tr * RED_TH + r;
@@ -751,8 +718,9 @@ void vm_kernel(const VmParams P) {
         next_fast = r + U < RED_TH && P.unit_cols &&
                     (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
       }
-      vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, next_fast, row0 + U,
-                                            sp_col[SPMV ? wib : 0], sp_val[SPMV ? wib : 0]);
+      vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS, false, false, PG>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode,
+                                                                    next_fast, row0 + U, sp_col[SPMV ? wib : 0],
+                                                                    sp_val[SPMV ? wib : 0]);
       have = next_fast;
     }
     // ---- tile sums into the block's LDS row ---------------------------------------
@@ -775,23 +743,25 @@ void vm_kernel(const VmParams P) {
   if (blk0 >= P.n_tiles) return;
   const int cnt = (int)min((int64_t)4 * P.tiles_per_wave, P.n_tiles - blk0);
   const T v = block_tree(tsum[wib], cnt, lane);
-  if (lane == 0) ((T*)P.red_partials[wib])[lb] = v;
+  if (lane == 0) {
+    if (P.red_direct) {
+      T* res = (T*)P.red_result[wib];
+      *res = P.red_init[wib] ? v : *res + v;
+    } else {
+      ((T*)P.red_partials[wib])[lb] = v;
+    }
+  }
 }
 
+#ifndef __HIPCC_RTC__
 // Launch one pass on a tier's kernels: element type, SpMV prologue and
 // stream bucket select the instantiation.
 template <int HV, int NR, int NB0, int NB1, int NB2, int ROWS = 0>
 int launch_tier(const VmParams& P, int is_f64, int nb, hipStream_t st) {
   const dim3 g(P.grid), b(BLOCK);
   const bool sp = P.spmv != 0;
-  // one-tile SpMV passes stage the tile's rows in dynamic LDS (same bytes
-  // for FP64 and FP32: RED_TH rows of 16 bytes per lane)
-  // stencil passes: per wave ST_RCH + 2 staged rows of TW elements and 16
-  // more bytes (the halo columns)
   const bool sten = HV == 0 && ROWS == 0 && !sp && P.st_n > 0 && nb != NB0;
-  const size_t dyn = sp && P.sp_coop ? (size_t)RED_TH * WAVE * 16
-                     : sten          ? (size_t)(BLOCK / WAVE) * ST_NBUF * (ST_RCH + 2) * (WAVE * 16 + 16)
-                                     : 0;
+  const size_t dyn = vm_dyn_lds_bytes(P, sten);
 #define DFX_L(T, SP)                                                                                \
   {                                                                                                 \
     if (nb == NB0) hipLaunchKernelGGL((vm_kernel<T, HV, SP, NR, NB0, ROWS>), g, b, dyn, st, P);     \
@@ -838,5 +808,7 @@ int tier_waves_per_cu(int is_f64, int nb) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, BLOCK, 0) != hipSuccess) return 0;
   return blocks * (BLOCK / WAVE);
 }
+
+#endif  // __HIPCC_RTC__
 
 }  // namespace dfx
