@@ -1286,6 +1286,22 @@ static bool red_direct(const Ctx& c, const PassPlan& p) {
   return on && !c.batch_rec && p.n_tiles >= 1 && p.n_tiles <= 4 * p.tiles_per_wave;
 }
 
+// Waves per tile of a pass without reductions (1, 2 or 4).  With one wave
+// per tile a pass of few tiles leaves most of the chip idle and each wave
+// walks its tile's 32 rows in sequence (the 256-tile passes of the GMG fine
+// level run 256 waves); splitting a tile's rows over 2 or 4 waves changes no
+// bit when nothing is reduced.  Stencil-staged passes stage whole tiles and
+// keep one wave.  DFX_ROW_SPLIT=0 turns it off.
+static int row_split_for(const PassPlan& p, const VmParams& P) {
+  const char* e = std::getenv("DFX_ROW_SPLIT");
+  if (e && e[0] == '0') return 1;
+  if (P.n_red != 0 || P.st_n != 0 || p.tiles_per_wave != 1 || p.kind == 2) return 1;
+  int s = p.n_tiles <= 1024 ? 4 : p.n_tiles <= 4096 ? 2 : 1;
+  // a lone tile of at most 8 rows has work for one wave only
+  if (p.n_tiles == 1 && p.rows <= RED_TH / 4) s = 1;
+  return s;
+}
+
 // Passes that run compiled when jit is on (measured on MI355X):
 // transcendental passes, where the interpreter's dispatch dominates
 // (Black-Scholes FP64 over 2^26 options: 0.79 against 1.05 ms); small
@@ -1308,6 +1324,12 @@ static std::shared_ptr<JitEntry> request_compiled(PassPlan& p, int st_n, int row
   g.code = p.code;
   g.out_reg = p.out_reg;
   g.bc_reg = p.bc_reg;
+  if (st_n > 0)
+    for (size_t a = 0; a < p.ins.size(); ++a) {
+      g.st_on.push_back(p.st_on[a]);
+      g.st_dr.push_back(p.st_dr[a]);
+      g.st_dc.push_back(p.st_dc[a]);
+    }
   const JitVariant v = jit_variant(p.dtype == DFX_F64, p.tier, (int)p.ins.size(), p.kind == 1, st_n, rows);
   std::string name;
   const std::string src = jit_source(v, g, &name);
@@ -1490,7 +1512,15 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.st_srow = p.st_srow;
     P.st_lim = ss.elems - p.st_off0;
   }
+  P.row_split = 1;
   if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
+  if (const int rs = row_split_for(p, P); rs > 1) {
+    P.row_split = rs;
+    P.sp_coop = 0;
+    int64_t grid = std::max<int64_t>(1, (p.n_tiles * rs + 3) / 4);
+    if (grid > 8) grid = (grid + 7) / 8 * 8;
+    P.grid = (int)grid;
+  }
   const int rows = pick_rows(c, p);
   // compiled kernel, once ready (module loading is kept out of captures)
   hipFunction_t fn = nullptr;

@@ -38,12 +38,14 @@ struct JitVariant {
   int spmv = 0;
   int sten = 0;    // stencil staging variant
   int waves = 2;   // waves-per-SIMD target given to the compiler
+  int heavy_pf = 0; // transcendental pass: load the next step during this one
 };
 
 // A pass's program: its instructions and register maps.
 struct JitProgram {
   std::vector<VmInstr> code;
   std::vector<int32_t> out_reg, bc_reg;
+  std::vector<int32_t> st_on, st_dr, st_dc;   // stencil staging map (empty: none)
 };
 
 struct JitEntry;
@@ -52,8 +54,9 @@ struct JitEntry;
 // prologue `spmv`, `st_n` staged streams and the planner's rows per step:
 // the interpreter's, except that transcendental passes take one row per
 // step (their straight-line code keeps few registers that way, so more
-// waves are resident).  DFX_JIT_ROWS (0, 1 or 2) and DFX_JIT_WAVES override
-// the choice for non-SpMV, unstaged passes.
+// waves are resident), and FP32 transcendental passes prefetch the next
+// step's loads.  DFX_JIT_ROWS (0, 1 or 2) and DFX_JIT_WAVES override the
+// choice for non-SpMV, unstaged passes, DFX_JIT_PF (0 or 1) the prefetch.
 JitVariant jit_variant(int is_f64, int tier, int n_in, int spmv, int st_n, int rows);
 
 // Source text of the pass's kernel and the name expression of its entry.

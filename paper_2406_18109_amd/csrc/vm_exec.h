@@ -158,15 +158,19 @@ __device__ __forceinline__ void vm_instr(typename GVec<T, GS>::type (&R0)[NR], t
 }
 
 // The op list a kernel executes.  VmInterp interprets the pass's code
-// (P.code, P.out_reg, P.bc_reg).  A compiled pass's program type, generated
-// by the host for that one pass, has COMPILED true, its output and
-// broadcast register maps as constants, its waves-per-SIMD target (WAVES)
-// and a run() that calls vm_instr for each instruction in order.
+// (P.code, P.out_reg, P.bc_reg, P.st_on/st_dr/st_dc).  A compiled pass's
+// program type, generated by the host for that one pass, has COMPILED true,
+// its output and broadcast register maps and its stencil staging map as
+// constants, its waves-per-SIMD target (WAVES), whether a transcendental
+// pass software-pipelines its loads (HEAVY_PF) and a run() that calls
+// vm_instr for each instruction in order.
 struct VmInterp {
   static constexpr bool COMPILED = false;
   static constexpr int WAVES = 1;
+  static constexpr bool HEAVY_PF = false;   // transcendental passes prefetch the next step
   static constexpr int out_reg[VM_MAXOUT] = {};
   static constexpr int bc_reg[VM_MAXBC] = {};
+  static constexpr int st_on[VM_MAXIN] = {}, st_dr[VM_MAXIN] = {}, st_dc[VM_MAXIN] = {};
   template <typename T, int HV, int NR, int NG, int GS, int E>
   static __device__ __forceinline__ void run(typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
                                              typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
@@ -287,8 +291,9 @@ __device__ __forceinline__ void vm_step(
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
       if (a >= P.n_in) break;
-      if (P.st_on[a]) {
-        const T* src = stl + (q + P.st_dr[a]) * PITCH + lane * V + P.st_dc[a];
+      if (PG::COMPILED ? PG::st_on[a] != 0 : P.st_on[a] != 0) {
+        const int dr = PG::COMPILED ? PG::st_dr[a] : P.st_dr[a], dc = PG::COMPILED ? PG::st_dc[a] : P.st_dc[a];
+        const T* src = stl + (q + dr) * PITCH + lane * V + dc;
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -654,8 +659,13 @@ void vm_kernel(const VmParams P) {
 #endif
   if ((P.grid & 7) == 0 && (!SPMV || DFX_SPMV_XCD_REMAP)) lb = (blockIdx.x & 7) * (P.grid >> 3) + (blockIdx.x >> 3);
   const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + wib;
-  const int64_t t_begin = gw * P.tiles_per_wave;
-  const int64_t t_end = min(t_begin + P.tiles_per_wave, P.n_tiles);
+  // rows [r_lo, r_hi) of each tile: all of them, or the wave's share of a
+  // tile under row_split (passes without reductions)
+  const int split = P.row_split > 1 ? P.row_split : 1;
+  const int64_t t_begin = split > 1 ? gw / split : gw * P.tiles_per_wave;
+  const int64_t t_end = min(t_begin + (split > 1 ? 1 : P.tiles_per_wave), P.n_tiles);
+  const int r_lo = split > 1 ? (int)(gw % split) * (RED_TH / split) : 0;
+  const int r_hi = r_lo + RED_TH / split;
 
   // Arithmetic passes are stream-bound: their loads are software-pipelined
   // one step ahead inside a tile (up to four streams: the wider bucket would
@@ -668,7 +678,7 @@ void vm_kernel(const VmParams P) {
 #ifndef DFX_HEAVY_PF
 #define DFX_HEAVY_PF 0
 #endif
-  constexpr bool PF = !SPMV && NINB <= DFX_PREFETCH_MAX_STREAMS && (!S::HEAVY || DFX_HEAVY_PF);
+  constexpr bool PF = !SPMV && NINB <= DFX_PREFETCH_MAX_STREAMS && (!S::HEAVY || DFX_HEAVY_PF || PG::HEAVY_PF);
   // FP32 transcendental kernels load through vm_load (padding slots
   // skipped).  The FP64 ones load straight into the register file: without
   // the separate load buffer they fit three waves per SIMD instead of two
@@ -689,11 +699,11 @@ void vm_kernel(const VmParams P) {
     if constexpr (STEN && !SPMV && HV == 0) {
       // stencil passes: a whole interior tile whose staged window lies in
       // the store goes through LDS (vm_stencil_tile)
-      staged = P.st_n > 0 && P.unit_cols && (tr + 1) * RED_TH <= P.rows && cbase + TW <= P.cols &&
+      staged = split == 1 && P.st_n > 0 && P.unit_cols && (tr + 1) * RED_TH <= P.rows && cbase + TW <= P.cols &&
                ((tr + 1) * RED_TH + 1) * P.st_srow + cbase + TW + 16 / (int)sizeof(T) <= P.st_lim;
       if (staged) vm_stencil_tile<T, HV, SPMV, NR, NINB, ROWS, PG>(P, R0, R1, R2, R3, G, L, tr, cbase, c0, wib);
     }
-    for (int r = 0; r < (staged ? 0 : RED_TH); r += U) {
+    for (int r = r_lo; r < (staged ? r_lo : r_hi); r += U) {
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= P.rows) break;
       const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
@@ -715,7 +725,7 @@ void vm_kernel(const VmParams P) {
         if (mode != MODE_SLOW && !(have && mode == MODE_FAST)) vm_load<T, V, U, E, NINB>(P, L, row0, c0, vmask, mode);
       if constexpr (PF) {
         const int64_t nr = row0 + U;
-        next_fast = r + U < RED_TH && P.unit_cols &&
+        next_fast = r + U < r_hi && P.unit_cols &&
                     (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
       }
       vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS, false, false, PG>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode,
