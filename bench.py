@@ -100,27 +100,25 @@ VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 def alu_roof(n, kernel_s):
     """The ALU roof of the Black-Scholes FP64 pass from the committed counter
     summary (profiles/traffic.json, taken on the current kernel source):
-    `math_valu_per_option` is the VALU instruction count of the op list's
-    arithmetic alone (a straight-line evaluation of the same chain with the
-    same math routines), `valu_per_option` what the op-list kernel executes
-    (SQ_INSTS_VALU x 64 / options).  Floors at the VALU issue peak, and the
-    achieved rate of the math instructions.  None without a current summary."""
+    `valu_per_option` is what the dominant kernel, the compiled pass, executes
+    (SQ_INSTS_VALU x 64 / options).  A compiled pass runs the chain as
+    straight-line code, so this is the pass's own arithmetic plus the tiling's
+    address and mask work.  Floor at the VALU issue peak, and the achieved
+    issue rate.  None without a current summary."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         e = json.load(fh).get("bs_f64_fused")
-    if not e or e.get("kernel_hash") != kernel_source_hash() or "math_valu_per_option" not in e:
+    if not e or e.get("kernel_hash") != kernel_source_hash() or "valu_per_option" not in e:
         return None
-    math_i = e["math_valu_per_option"]
-    cnt = e.get("valu_per_option")
-    ach = math_i * n / kernel_s
+    cnt = e["valu_per_option"]
+    ach = cnt * n / kernel_s
     out = {"unit": "T lane-instr/s", "peak": round(VALU_PEAK_LANE_INSTR / 1e12, 2),
-           "math_valu_per_option": math_i, "math_floor_ms": round(math_i * n / VALU_PEAK_LANE_INSTR * 1e3, 4),
+           "valu_per_option": cnt, "valu_floor_ms": round(cnt * n / VALU_PEAK_LANE_INSTR * 1e3, 4),
            "achieved": round(ach / 1e12, 3), "frac": round(ach / VALU_PEAK_LANE_INSTR, 4)}
-    if cnt is not None:
-        out["valu_per_option"] = cnt
-        out["valu_issue_frac"] = round(cnt * n / kernel_s / VALU_PEAK_LANE_INSTR, 4)
+    if "salu_per_option" in e:
+        out["salu_per_option"] = e["salu_per_option"]
     return out
 
 
@@ -848,7 +846,7 @@ def main():
     alu = alu_roof(n, kernel_s)
     if alu is not None:
         roof["alu"] = alu
-        if alu["math_floor_ms"] * 1e-3 > hbm_floor:
+        if alu["valu_floor_ms"] * 1e-3 > hbm_floor:
             # the op list's own arithmetic takes longer at the VALU peak than
             # its bytes at the HBM peak: the pass is ALU-bound
             roof.update(bound="alu", achieved=alu["achieved"], peak=alu["peak"], unit=alu["unit"],

@@ -1286,19 +1286,22 @@ static bool red_direct(const Ctx& c, const PassPlan& p) {
   return on && !c.batch_rec && p.n_tiles >= 1 && p.n_tiles <= 4 * p.tiles_per_wave;
 }
 
-// Waves per tile of a pass without reductions (1, 2 or 4).  With one wave
-// per tile a pass of few tiles leaves most of the chip idle and each wave
-// walks its tile's 32 rows in sequence (the 256-tile passes of the GMG fine
-// level run 256 waves); splitting a tile's rows over 2 or 4 waves changes no
-// bit when nothing is reduced.  Stencil-staged passes stage whole tiles and
-// keep one wave.  DFX_ROW_SPLIT=0 turns it off.
+// Waves per tile of a pass without reductions (a power of two up to 32).
+// With one wave per tile a pass of few tiles leaves most of the chip idle
+// and each wave walks its tile's 32 rows in sequence (the 256-tile passes
+// of the GMG fine level ran 256 waves); splitting a tile's rows over several
+// waves changes no bit when nothing is reduced.  The split aims at about
+// 8192 waves per pass, down to one row per wave for SpMV passes (one row
+// per step) and two otherwise (two-row steps).  Stencil-staged passes stage
+// whole tiles and keep one wave.  DFX_ROW_SPLIT=<n> caps it (0 or 1: off).
 static int row_split_for(const PassPlan& p, const VmParams& P) {
-  const char* e = std::getenv("DFX_ROW_SPLIT");
-  if (e && e[0] == '0') return 1;
+  int cap = p.kind == 1 ? RED_TH : RED_TH / 2;
+  if (const char* e = std::getenv("DFX_ROW_SPLIT")) cap = std::max(1, std::min(cap, std::atoi(e)));
   if (P.n_red != 0 || P.st_n != 0 || p.tiles_per_wave != 1 || p.kind == 2) return 1;
-  int s = p.n_tiles <= 1024 ? 4 : p.n_tiles <= 4096 ? 2 : 1;
-  // a lone tile of at most 8 rows has work for one wave only
-  if (p.n_tiles == 1 && p.rows <= RED_TH / 4) s = 1;
+  int s = 1;
+  while (2 * s <= cap && p.n_tiles * 2 * s <= 8192) s *= 2;
+  // a lone tile of one row has work for one wave only
+  if (p.n_tiles == 1 && p.rows <= 1) s = 1;
   return s;
 }
 
@@ -1314,7 +1317,9 @@ static int row_split_for(const PassPlan& p, const VmParams& P) {
 static bool jit_wanted(const PassPlan& p, int st_n) {
   const char* all = std::getenv("DFX_JIT_ALL");
   if (all && all[0] == '1') return true;
-  return p.tier != TIER_ARITH || p.n_tiles < 256 || st_n > 0;
+  int64_t small = 256;
+  if (const char* e = std::getenv("DFX_JIT_SMALL")) small = std::atoll(e);
+  return p.tier != TIER_ARITH || p.n_tiles < small || st_n > 0;
 }
 
 // The pass's program and kernel variant for compilation (rows: the rows per

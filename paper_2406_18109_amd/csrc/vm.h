@@ -124,9 +124,10 @@ struct VmParams {
   int64_t n1d;
   int64_t n_tiles, strips;  // tiles, tiles per tile-row
   int64_t tiles_per_wave;  // power of two, at most VM_MAXTPW
-  // row_split (1, 2 or 4; passes without reductions, one tile per wave):
-  // waves per tile, wave k of a tile taking rows [k, k + 1) * RED_TH /
-  // row_split.  No reduction order is involved, so the split changes no bit.
+  // row_split (a power of two dividing RED_TH, a multiple of the rows per
+  // step; passes without reductions, one tile per wave): waves per tile,
+  // wave k of a tile taking rows [k, k + 1) * RED_TH / row_split.  No
+  // reduction order is involved, so the split changes no bit.
   int32_t row_split;
   VmStream in[VM_MAXIN];
   VmStream out[VM_MAXOUT];
