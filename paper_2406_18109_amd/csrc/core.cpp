@@ -1217,11 +1217,19 @@ static int build_plan(Ctx& c, int f, const std::set<int64_t>& temps, const std::
 
 static void* g_dummy_stream = nullptr;  // zeroed 4 KB read by padding stream slots
 
+// Block sums a pass's workspace holds per reduction: one per block, or one
+// per tile when a compiled pass gives every tile its own block (red_split,
+// at most RED_SPLIT_MAX_TILES tiles).
+constexpr int64_t RED_SPLIT_MAX_TILES = 2048;
+static size_t block_sum_slots(const PassPlan& p) {
+  return (size_t)std::max<int64_t>(p.grid, p.n_tiles <= RED_SPLIT_MAX_TILES ? p.n_tiles : 0);
+}
+
 static int ensure_workspace(Ctx& c, PassPlan& p) {
   if (c.analysis_only || p.red_cstore.empty() || p.ws) return DFX_OK;
   if (c.capturing) return fail(c, DFX_ESTATE, "a new fused window appeared while a graph is being recorded");
   const size_t es = dtype_size(p.dtype);
-  const size_t part = ((size_t)p.grid * es + 255) / 256 * 256;  // one sum per block
+  const size_t part = (block_sum_slots(p) * es + 255) / 256 * 256;  // one sum per block
   p.ws_bytes = part * p.red_cstore.size();
   p.ws = dev_alloc(c, p.ws_bytes);
   if (!p.ws) return fail(c, DFX_ENOMEM, "workspace allocation failed");
@@ -1275,6 +1283,18 @@ static bool stencil_enabled() {
   return on;
 }
 
+// Whether a compiled pass runs each tile on a block of four waves
+// (red_split): one reduction, one tile per wave, no staging or row split,
+// and either a lone tile or more tiles than one block holds (so that the
+// block-sum launch is needed either way) up to RED_SPLIT_MAX_TILES.
+// DFX_RED_SPLIT=0 turns it off.
+static bool red_split_ok(const PassPlan& p, const VmParams& P) {
+  const char* e = std::getenv("DFX_RED_SPLIT");
+  if (e && e[0] == '0') return false;
+  return P.n_red == 1 && P.st_n == 0 && P.row_split <= 1 && p.tiles_per_wave == 1 && p.kind != 2 &&
+         (p.n_tiles == 1 || (p.n_tiles > 4 && p.n_tiles <= RED_SPLIT_MAX_TILES)) && block_sum_slots(p) >= (size_t)p.n_tiles;
+}
+
 // A reducing pass whose tiles all belong to block 0 (one block sum) writes
 // its 0-d results from that block; not when recorded into a batch (the
 // batched executor reduces tile sums itself).  DFX_RED_DIRECT=0 turns it off.
@@ -1284,6 +1304,44 @@ static bool red_direct(const Ctx& c, const PassPlan& p) {
     return !(e && e[0] == '0');
   }();
   return on && !c.batch_rec && p.n_tiles >= 1 && p.n_tiles <= 4 * p.tiles_per_wave;
+}
+
+// Blocks of four waves for `waves` waves (a multiple of 8 beyond 8 blocks,
+// for the kernel's XCD-contiguous block numbering).
+static int grid_for(int64_t waves) {
+  int64_t grid = std::max<int64_t>(1, (waves + 3) / 4);
+  if (grid > 8) grid = (grid + 7) / 8 * 8;
+  return (int)grid;
+}
+
+// Columns by which a 2-D pass without reductions starts its strips early so
+// that its 16-byte vectors are aligned (0: none).  A view that starts inside
+// a 16-byte word (the interior of a grid, one element in) has every vector
+// access straddle two words.  Shifting pays only when every stream, input
+// and output, has the same offset (an in-place update of an interior view):
+// for the Jacobi sweep's copy from an aligned array into the grid interior,
+// moving the misalignment from the stores to the loads made the sweep slower
+// (0.471 against 0.457 ms).  Row strides must keep the offset.
+// DFX_COL_SHIFT=0 turns it off.
+static int col_shift_for(const PassPlan& p, const VmParams& P, size_t es) {
+  const char* e = std::getenv("DFX_COL_SHIFT");
+  if (e && e[0] == '0') return 0;
+  if (p.kind != 0 || p.is1d || P.n_red != 0 || P.st_n != 0 || !p.unit_cols || P.n_out == 0) return 0;
+  const int64_t V = 16 / (int64_t)es;
+  int64_t mis = -1;
+  auto same = [&](const VmStream& st) {
+    const uintptr_t a = (uintptr_t)st.base;
+    if (a % es != 0 || st.s_row % V != 0 || st.s_col != 1) return false;
+    const int64_t m = (int64_t)((a / es) % (uintptr_t)V);
+    if (mis >= 0 && m != mis) return false;
+    mis = m;
+    return true;
+  };
+  for (int k = 0; k < P.n_out; ++k)
+    if (!same(P.out[k])) return 0;
+  for (int k = 0; k < P.n_in; ++k)
+    if (!same(P.in[k])) return 0;
+  return mis > 0 ? (int)mis : 0;
 }
 
 // Waves per tile of a pass without reductions (a power of two up to 32).
@@ -1297,11 +1355,11 @@ static bool red_direct(const Ctx& c, const PassPlan& p) {
 static int row_split_for(const PassPlan& p, const VmParams& P) {
   int cap = p.kind == 1 ? RED_TH : RED_TH / 2;
   if (const char* e = std::getenv("DFX_ROW_SPLIT")) cap = std::max(1, std::min(cap, std::atoi(e)));
-  if (P.n_red != 0 || P.st_n != 0 || p.tiles_per_wave != 1 || p.kind == 2) return 1;
+  if (P.n_red != 0 || P.st_n != 0 || P.tiles_per_wave != 1 || p.kind == 2) return 1;
   int s = 1;
-  while (2 * s <= cap && p.n_tiles * 2 * s <= 8192) s *= 2;
+  while (2 * s <= cap && P.n_tiles * 2 * s <= 8192) s *= 2;
   // a lone tile of one row has work for one wave only
-  if (p.n_tiles == 1 && p.rows <= 1) s = 1;
+  if (P.n_tiles == 1 && p.rows <= 1) s = 1;
   return s;
 }
 
@@ -1471,7 +1529,7 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.bc[k] = S(p.bc_cstore[k]).ptr;
     P.bc_reg[k] = p.bc_reg[k];
   }
-  const size_t part = ((size_t)p.grid * es + 255) / 256 * 256;
+  const size_t part = (block_sum_slots(p) * es + 255) / 256 * 256;
   VmFinal F;
   std::memset(&F, 0, sizeof(F));
   F.n_red = P.n_red;
@@ -1518,13 +1576,23 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.st_lim = ss.elems - p.st_off0;
   }
   P.row_split = 1;
+  P.col_shift = 0;
   if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
+  // column shift (aligned output vectors), then row split, of passes
+  // without reductions; either changes the launch shape only
+  if (const int cs = col_shift_for(p, P, es); cs > 0) {
+    const int64_t TWp = p.dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW;
+    const int64_t row_tiles = p.n_tiles / std::max<int64_t>(1, p.strips);
+    P.col_shift = cs;
+    P.vec_cols = 0;
+    P.strips = (p.cols + cs + TWp - 1) / TWp;
+    P.n_tiles = row_tiles * P.strips;
+    P.grid = grid_for((P.n_tiles + p.tiles_per_wave - 1) / p.tiles_per_wave);
+  }
   if (const int rs = row_split_for(p, P); rs > 1) {
     P.row_split = rs;
     P.sp_coop = 0;
-    int64_t grid = std::max<int64_t>(1, (p.n_tiles * rs + 3) / 4);
-    if (grid > 8) grid = (grid + 7) / 8 * 8;
-    P.grid = (int)grid;
+    P.grid = grid_for(P.n_tiles * rs);
   }
   const int rows = pick_rows(c, p);
   // compiled kernel, once ready (module loading is kept out of captures)
@@ -1535,6 +1603,14 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
       if (jit_wanted(p, P.st_n)) p.jit = request_compiled(p, P.st_n, rows, c.cfg.jit == 2);
     }
     if (p.jit) fn = jit_function(*p.jit, c.cfg.device, !c.capturing);
+  }
+  // a compiled pass of one reduction and few tiles gives each tile a block
+  // of four waves (red_split; bit-identical tile sums)
+  if (fn && red_split_ok(p, P)) {
+    P.red_split = 1;
+    P.sp_coop = 0;
+    P.grid = (int)p.n_tiles;
+    F.nblocks = (int)p.n_tiles;
   }
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
   int e;

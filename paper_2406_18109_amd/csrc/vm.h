@@ -129,6 +129,16 @@ struct VmParams {
   // wave k of a tile taking rows [k, k + 1) * RED_TH / row_split.  No
   // reduction order is involved, so the split changes no bit.
   int32_t row_split;
+  // red_split (compiled passes with one reduction, one tile per block): the
+  // block's four waves take a quarter of its tile's rows each and stage the
+  // reduction's summands in dynamic LDS; wave 0 then adds them in the
+  // canonical order, so the tile sum has the bits of one wave's
+  int32_t red_split;
+  // col_shift (2-D passes without reductions, 0 <= col_shift < V): strips
+  // start col_shift columns early (strip s covers columns [s * TW -
+  // col_shift, (s + 1) * TW - col_shift)), so that the output streams' 16-byte
+  // vectors are aligned; columns outside [0, cols) are masked.
+  int32_t col_shift;
   VmStream in[VM_MAXIN];
   VmStream out[VM_MAXOUT];
   int32_t out_reg[VM_MAXOUT];
@@ -163,11 +173,12 @@ struct VmParams {
 };
 
 // Dynamic LDS bytes of a pass's launch: a one-tile SpMV pass stages the
-// tile's rows (RED_TH rows of 16 bytes per lane, FP64 and FP32 alike); a
+// tile's rows, a red_split pass its reduction's summands (either way RED_TH
+// rows of 16 bytes per lane, FP64 and FP32 alike); a
 // stencil-staged pass gives each wave ST_NBUF buffers of ST_RCH + 2 rows of
 // TW elements plus 16 bytes of halo.
 inline size_t vm_dyn_lds_bytes(const VmParams& P, bool sten) {
-  return P.spmv && P.sp_coop ? (size_t)RED_TH * WAVE * 16
+  return (P.spmv && P.sp_coop) || P.red_split ? (size_t)RED_TH * WAVE * 16
          : sten              ? (size_t)(BLOCK / WAVE) * ST_NBUF * (ST_RCH + 2) * (WAVE * 16 + 16)
                              : 0;
 }

@@ -137,6 +137,12 @@ template <typename T, int NG, int GS> struct VmState {
   typedef typename GVec<T, GS>::type gvec;
   gvec z[NG];               // previous instruction's result (forwarded operand)
   T acc0, acc1, acc2, acc3; // this lane's reduction accumulators
+  // A tile shared by a block's waves (compiled passes, red_split): reduction
+  // slot 0 writes its summands to dsum[(drow + u) * TW + lane * V + v] (drow:
+  // the step's first row within the tile) instead of accumulating them.
+  // Set by compiled kernels only (the interpreter never reads them).
+  T* dsum;
+  int drow;
 };
 
 // One instruction of the op list over every element slot of a step, for
@@ -153,6 +159,8 @@ __device__ __forceinline__ void vm_instr(typename GVec<T, GS>::type (&R0)[NR], t
                                          const unsigned d, const unsigned ia, const unsigned ib, const unsigned ic,
                                          const T k) {
   constexpr bool HEAVY = HV > 0;
+  constexpr bool DEFER_OK = true;
+  constexpr int V = Lanes<T>::V, TW = Lanes<T>::TW;
   typedef typename GVec<T, GS>::type gvec;
 #include "vm_instr.inc"
 }
@@ -407,6 +415,7 @@ __device__ __forceinline__ void vm_step(
   if constexpr (PG::COMPILED) {
     PG::template run<T, HV, NR, NG, GS, E>(R0, R1, R2, R3, G, vmask);
   } else {
+  constexpr bool DEFER_OK = false;
   VmInstr nx = P.code[0];
   for (int pc = 0; pc < P.n_code; ++pc) {
     const unsigned w0 = __builtin_amdgcn_readfirstlane(nx.w0), w1 = __builtin_amdgcn_readfirstlane(nx.w1);
@@ -661,11 +670,14 @@ void vm_kernel(const VmParams P) {
   const int64_t gw = (int64_t)lb * (BLOCK / WAVE) + wib;
   // rows [r_lo, r_hi) of each tile: all of them, or the wave's share of a
   // tile under row_split (passes without reductions)
+  // (red_split, compiled passes with one reduction: block lb owns tile lb
+  // and its four waves take a quarter of the rows each)
   const int split = P.row_split > 1 ? P.row_split : 1;
-  const int64_t t_begin = split > 1 ? gw / split : gw * P.tiles_per_wave;
-  const int64_t t_end = min(t_begin + (split > 1 ? 1 : P.tiles_per_wave), P.n_tiles);
-  const int r_lo = split > 1 ? (int)(gw % split) * (RED_TH / split) : 0;
-  const int r_hi = r_lo + RED_TH / split;
+  const bool rsplit = PG::COMPILED && P.red_split != 0;
+  const int64_t t_begin = rsplit ? (int64_t)lb : split > 1 ? gw / split : gw * P.tiles_per_wave;
+  const int64_t t_end = min(t_begin + ((split > 1 || rsplit) ? 1 : P.tiles_per_wave), P.n_tiles);
+  const int r_lo = rsplit ? wib * (RED_TH / 4) : split > 1 ? (int)(gw % split) * (RED_TH / split) : 0;
+  const int r_hi = r_lo + (rsplit ? RED_TH / 4 : RED_TH / split);
 
   // Arithmetic passes are stream-bound: their loads are software-pipelined
   // one step ahead inside a tile (up to four streams: the wider bucket would
@@ -691,9 +703,13 @@ void vm_kernel(const VmParams P) {
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int64_t tr = t / P.strips;
     const int64_t ts = t - tr * P.strips;
-    const int64_t cbase = ts * TW;
+    const int64_t cbase = ts * TW - P.col_shift;
     const int64_t c0 = cbase + (int64_t)lane * V;
     G.acc0 = G.acc1 = G.acc2 = G.acc3 = (T)0;
+    if constexpr (PG::COMPILED) {
+      extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
+      G.dsum = rsplit ? (T*)vm_dyn_lds : nullptr;
+    }
     bool have = false;  // L already holds this step's values (prefetched)
     bool staged = false;
     if constexpr (STEN && !SPMV && HV == 0) {
@@ -707,7 +723,7 @@ void vm_kernel(const VmParams P) {
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= P.rows) break;
       const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
-                                   : (row0 + U <= P.rows && cbase + TW <= P.cols);
+                                   : (row0 + U <= P.rows && cbase >= 0 && cbase + TW <= P.cols);
       int mode = MODE_FAST;
       unsigned vmask = (1u << E) - 1;
       if (!(P.unit_cols && interior)) {
@@ -716,7 +732,7 @@ void vm_kernel(const VmParams P) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const int64_t row = row0 + e / V, col = c0 + e % V;
-          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col < P.cols);
+          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col >= 0 && col < P.cols);
           vmask |= (ok ? 1u : 0u) << e;
         }
       }
@@ -726,15 +742,16 @@ void vm_kernel(const VmParams P) {
       if constexpr (PF) {
         const int64_t nr = row0 + U;
         next_fast = r + U < r_hi && P.unit_cols &&
-                    (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase + TW <= P.cols));
+                    (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase >= 0 && cbase + TW <= P.cols));
       }
+      if constexpr (PG::COMPILED) G.drow = r;
       vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS, false, false, PG>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode,
                                                                     next_fast, row0 + U, sp_col[SPMV ? wib : 0],
                                                                     sp_val[SPMV ? wib : 0]);
       have = next_fast;
     }
     // ---- tile sums into the block's LDS row ---------------------------------------
-    if (P.n_red > 0) {
+    if (P.n_red > 0 && !rsplit) {
       const int j = wib * (int)P.tiles_per_wave + (int)(t - t_begin);
       T a0 = wave_sum(G.acc0);
       if (lane == 0) tsum[0][j] = a0;
@@ -745,6 +762,39 @@ void vm_kernel(const VmParams P) {
   }
 
   if (P.n_red == 0) return;
+  if constexpr (PG::COMPILED) {
+    if (rsplit) {
+      // the block's one tile: wave 0 adds the summands lane by lane over the
+      // tile's rows, then columns (valid elements only), the order in which
+      // one wave would have accumulated them; the tile sum is the block sum
+      __syncthreads();
+      if (wib != 0 || t_begin >= P.n_tiles) return;
+      extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
+      const T* ds = (const T*)vm_dyn_lds;
+      const int64_t tr = t_begin / P.strips;
+      const int64_t c0 = (t_begin - tr * P.strips) * TW - P.col_shift + (int64_t)lane * V;
+      T acc = (T)0;
+      for (int r = 0; r < RED_TH; ++r) {
+        const int64_t row = tr * RED_TH + r;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int64_t col = c0 + v;
+          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col >= 0 && col < P.cols);
+          if (ok) acc = acc + ds[r * TW + lane * V + v];
+        }
+      }
+      const T v = wave_sum(acc);
+      if (lane == 0) {
+        if (P.red_direct) {
+          T* res = (T*)P.red_result[0];
+          *res = P.red_init[0] ? v : *res + v;
+        } else {
+          ((T*)P.red_partials[0])[lb] = v;
+        }
+      }
+      return;
+    }
+  }
   // ---- block subtree: the 4 * tiles_per_wave tiles from lb * 4 * tiles_per_wave
   // form one aligned subtree of the tile tree; wave k reduces reduction k.
   __syncthreads();

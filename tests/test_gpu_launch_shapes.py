@@ -1,0 +1,107 @@
+"""Launch shapes that must not change a bit, each against its own switch:
+row_split (waves per tile of passes without reductions), col_shift (strips
+started early so that views misaligned alike access aligned vectors) and
+red_split (compiled passes with one reduction: a block of four waves per
+tile, summands added in the canonical order).  Every workload runs with the
+shape on and with it off and must give identical results; the misaligned
+views are also checked against numpy."""
+import numpy as np
+import pytest
+
+import paper_2406_18109_amd as dfx
+import synth
+from gpu_util import note, upload
+from test_gpu_parity import cg_gpu, jacobi_gpu
+
+pytestmark = pytest.mark.gpu
+
+SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT")
+
+
+def _runs(monkeypatch, fn, jit):
+    """fn() with every shape on, then with each switched off in turn."""
+    out = []
+    for off in (None,) + SWITCHES:
+        for s in SWITCHES:
+            monkeypatch.delenv(s, raising=False)
+        if off:
+            monkeypatch.setenv(off, "0")
+        if jit:
+            monkeypatch.setenv("DFX_JIT", "2")
+        else:
+            monkeypatch.delenv("DFX_JIT", raising=False)
+        out.append((off, fn()))
+    for s in SWITCHES + ("DFX_JIT",):
+        monkeypatch.delenv(s, raising=False)
+    return out
+
+
+def _same(results):
+    (_, ref) = results[0]
+    for off, r in results[1:]:
+        for a, b in zip(ref, r):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), off
+
+
+@pytest.mark.parametrize("jit", [0, 2])
+def test_jacobi_shapes(monkeypatch, jit):
+    note("shapes jacobi 131 jit=%d" % jit)
+
+    def run():
+        grid, res, c = jacobi_gpu(131, 3, read_every=True)
+        c.close()
+        return grid, res
+    _same(_runs(monkeypatch, run, jit))
+
+
+@pytest.mark.parametrize("jit", [0, 2])
+@pytest.mark.parametrize("m", [40, 150])
+def test_cg_shapes(monkeypatch, jit, m):
+    note("shapes cg %d jit=%d" % (m, jit))
+
+    def run():
+        _, rho, x, c = cg_gpu(m, 6)
+        c.close()
+        return rho, x
+    _same(_runs(monkeypatch, run, jit))
+
+
+@pytest.mark.parametrize("dtype,cols", [("f32", 1032), ("f64", 1030)])
+@pytest.mark.parametrize("off", [(1, 1), (0, 1), (2, 3)])
+def test_misaligned_views(monkeypatch, dtype, cols, off):
+    """y[v] = a[v] + 2 b[v] and z[v] = a[v] * b[v] through one view v at
+    `off`: every stream's vectors start inside a 16-byte word unless the
+    strips are shifted."""
+    note("shapes misaligned %s off=%s" % (dtype, off))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    R = 70
+    h, w = R - 3, cols - 3
+    A = synth.uniform(11, 0, R * cols, -1.0, 1.0).astype(npdt).reshape(R, cols)
+    B = synth.uniform(11, 1, R * cols, -1.0, 1.0).astype(npdt).reshape(R, cols)
+
+    def run():
+        c = dfx.Context(device=0, window_size=8)
+        ha, hb = upload(c, A), upload(c, B)
+        hy = upload(c, np.zeros((R, cols), npdt))
+        hz = upload(c, np.zeros((R, cols), npdt))
+        T0 = c.part_tiling([h, w])
+        V = c.part_tiling([h, w], list(off))
+        t = c.store_create([h, w], dtype)
+        c.submit("mul_imm", [1, 1], [(hb, V, "R"), (t, T0, "W")], (2.0,))
+        c.submit("add", [1, 1], [(ha, V, "R"), (t, T0, "R"), (hy, V, "W")])
+        c.submit("mul", [1, 1], [(ha, V, "R"), (hb, V, "R"), (hz, V, "W")])
+        c.store_release(t)
+        y = c.store_read(hy, [R, cols], dtype)
+        z = c.store_read(hz, [R, cols], dtype)
+        c.close()
+        return y, z
+    res = _runs(monkeypatch, run, 0)
+    _same(res)
+    y, z = res[0][1]
+    r0, c0 = off
+    sa, sb = A[r0:r0 + h, c0:c0 + w], B[r0:r0 + h, c0:c0 + w]
+    ey = np.zeros((R, cols), npdt)
+    ez = np.zeros((R, cols), npdt)
+    ey[r0:r0 + h, c0:c0 + w] = sa + sb * npdt(2.0)
+    ez[r0:r0 + h, c0:c0 + w] = sa * sb
+    assert np.array_equal(y, ey) and np.array_equal(z, ez)
