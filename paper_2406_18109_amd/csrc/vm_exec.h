@@ -176,7 +176,6 @@ struct VmInterp {
   static constexpr bool COMPILED = false;
   static constexpr int WAVES = 1;
   static constexpr bool HEAVY_PF = false;   // transcendental passes prefetch the next step
-  static constexpr bool DEFER = false;      // reductions may defer their summands (VmState::dsum)
   static constexpr int out_reg[VM_MAXOUT] = {};
   static constexpr int bc_reg[VM_MAXBC] = {};
   static constexpr int st_on[VM_MAXIN] = {}, st_dr[VM_MAXIN] = {}, st_dc[VM_MAXIN] = {};
@@ -184,12 +183,6 @@ struct VmInterp {
   static __device__ __forceinline__ void run(typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
                                              typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
                                              VmState<T, NG, GS>&, unsigned) {}
-};
-
-// The interpreter with deferrable reductions (the batched executor's quarter
-// work items).
-struct VmInterpDefer : VmInterp {
-  static constexpr bool DEFER = true;
 };
 
 enum StepMode { MODE_FAST = 0, MODE_CLAMP = 1, MODE_SLOW = 2 };
@@ -422,7 +415,7 @@ __device__ __forceinline__ void vm_step(
   if constexpr (PG::COMPILED) {
     PG::template run<T, HV, NR, NG, GS, E>(R0, R1, R2, R3, G, vmask);
   } else {
-  constexpr bool DEFER_OK = PG::DEFER;
+  constexpr bool DEFER_OK = false;
   VmInstr nx = P.code[0];
   for (int pc = 0; pc < P.n_code; ++pc) {
     const unsigned w0 = __builtin_amdgcn_readfirstlane(nx.w0), w1 = __builtin_amdgcn_readfirstlane(nx.w1);
