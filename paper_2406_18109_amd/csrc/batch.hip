@@ -144,9 +144,9 @@ __device__ void run_tiles(const BatchPass& B, const BatchStream& st, int64_t r, 
           vmask |= (ok ? 1u : 0u) << e;
         }
       }
-      if (mode != MODE_SLOW) vm_load<BT, V, U, E, BNINB>(P, L, row0, c0, vmask, mode);
+      if (mode != MODE_SLOW) vm_load<BT, V, U, E, BNINB>(P, L, row0, c0, vmask, mode, cbase);
       vm_step<BT, BHV, true, BNR, BNINB, true, 0, true>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode, false, 0,
-                                                       scol, sval);
+                                                       scol, sval, nullptr, 0, cbase);
     }
     if (P.n_red > 0) {
       const double a0 = wave_sum(G.acc0);

@@ -1384,6 +1384,8 @@ static bool jit_wanted(const PassPlan& p, int st_n) {
 // step the interpreter would take).
 static std::shared_ptr<JitEntry> request_compiled(PassPlan& p, int st_n, int rows, bool sync) {
   JitProgram g;
+  g.n_in = (int)p.ins.size();
+  g.n_out = (int)p.outs.size();
   g.code = p.code;
   g.out_reg = p.out_reg;
   g.bc_reg = p.bc_reg;

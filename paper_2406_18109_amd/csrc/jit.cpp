@@ -314,6 +314,7 @@ std::string jit_source(const JitVariant& v, const JitProgram& g, std::string* na
   s += "  static constexpr bool COMPILED = true;\n";
   s += "  static constexpr int WAVES = " + std::to_string(v.waves) + ";\n";
   s += std::string("  static constexpr bool HEAVY_PF = ") + (v.heavy_pf ? "true" : "false") + ";\n";
+  s += "  static constexpr int N_IN = " + std::to_string(g.n_in) + ", N_OUT = " + std::to_string(g.n_out) + ";\n";
   s += "  static constexpr int out_reg[VM_MAXOUT] = " + int_list(g.out_reg, VM_MAXOUT) + ";\n";
   s += "  static constexpr int bc_reg[VM_MAXBC] = " + int_list(g.bc_reg, VM_MAXBC) + ";\n";
   s += "  static constexpr int st_on[VM_MAXIN] = " + int_list(g.st_on, VM_MAXIN) + ";\n";

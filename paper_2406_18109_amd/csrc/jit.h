@@ -43,6 +43,7 @@ struct JitVariant {
 
 // A pass's program: its instructions and register maps.
 struct JitProgram {
+  int n_in = 0, n_out = 0;   // input and output streams
   std::vector<VmInstr> code;
   std::vector<int32_t> out_reg, bc_reg;
   std::vector<int32_t> st_on, st_dr, st_dc;   // stencil staging map (empty: none)

@@ -174,6 +174,7 @@ __device__ __forceinline__ void vm_instr(typename GVec<T, GS>::type (&R0)[NR], t
 // vm_instr for each instruction in order.
 struct VmInterp {
   static constexpr bool COMPILED = false;
+  static constexpr int N_IN = 0, N_OUT = 0;   // (compiled passes: the pass's stream counts)
   static constexpr int WAVES = 1;
   static constexpr bool HEAVY_PF = false;   // transcendental passes prefetch the next step
   static constexpr int out_reg[VM_MAXOUT] = {};
@@ -219,24 +220,76 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
   rows_to_owners<T, V>(y, out);
 }
 
+// The parameter block a compiled pass's step reads.  The straight-line op
+// list keeps its constants in scalar registers; stream descriptors and
+// bounds held live across the tile loop as well would be spilled to vector
+// lanes and read back by VALU instructions at every step.  Offsetting the
+// block's address by a zero the compiler cannot see through makes each step
+// load what it uses again, with scalar loads from the kernel-argument
+// segment.
+template <class PG> __device__ __forceinline__ const VmParams& step_params(const VmParams& P) {
+  if constexpr (PG::COMPILED) {
+    typedef const __attribute__((address_space(4))) char* KB;
+    int64_t off = 0;
+    asm volatile("" : "+s"(off));
+    return *(const VmParams*)((KB)&P + off);
+  } else {
+    return P;
+  }
+}
+
+// Address of element (row, cbase) of a stream; a lane adds its 32-bit byte
+// offset, so that a compiled pass's fast-mode access is one instruction with
+// a scalar base and a vector offset (no per-lane 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ const char* row_base(const VmStream& s, int64_t row, int64_t cbase) {
+  return (const char*)s.base + (row * s.s_row + cbase) * (int64_t)sizeof(T);
+}
+
+// Input and output streams of a pass (compile-time for compiled passes).
+template <class PG> __device__ __forceinline__ int n_in_of(const VmParams& P) {
+  return PG::COMPILED ? PG::N_IN : P.n_in;
+}
+template <class PG> __device__ __forceinline__ int n_out_of(const VmParams& P) {
+  return PG::COMPILED ? PG::N_OUT : P.n_out;
+}
+
 // Vector-mode loads of one step (MODE_FAST or MODE_CLAMP) into L: every
 // stream's loads issued back to back before the first wait.  Padding slots
 // of the stream bucket are not loaded: their registers are free registers of
 // the pass, written before they are read.
-template <typename T, int V, int U, int E, int NINB>
+template <typename T, int V, int U, int E, int NINB, class PG = VmInterp>
 __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int64_t row0, int64_t c0, unsigned vmask,
-                                        const int mode) {
+                                        const int mode, const int64_t cbase) {
   typedef T vecA __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  const VmParams& Q = step_params<PG>(P);
+  if constexpr (PG::COMPILED) {
+    if (mode == MODE_FAST) {
+      // (cbase: the step's first column, c0 - lane * V)
+      const uint32_t loff = (uint32_t)((threadIdx.x & (WAVE - 1)) * V * sizeof(T));
+#pragma unroll
+      for (int a = 0; a < NINB; ++a) {
+        if (a >= n_in_of<PG>(P)) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const vecA w = *(const vecA*)(row_base<T>(Q.in[a], row0 + u, cbase) + loff);
+#pragma unroll
+          for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
+        }
+      }
+      return;
+    }
+  }
   bool okv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
 #pragma unroll
   for (int a = 0; a < NINB; ++a) {
-    if (a >= P.n_in) break;
-    const T* b = (const T*)P.in[a].base;
+    if (a >= n_in_of<PG>(P)) break;
+    const T* b = (const T*)Q.in[a].base;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const T* p = b + (row0 + u) * P.in[a].s_row + c0;
+      const T* p = b + (row0 + u) * Q.in[a].s_row + c0;
       if (mode == MODE_CLAMP) p = okv[u] ? p : b;
       const vecA w = *(const vecA*)p;
 #pragma unroll
@@ -245,9 +298,11 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
   }
   if (mode == MODE_CLAMP) {
 #pragma unroll
-    for (int a = 0; a < NINB; ++a)
+    for (int a = 0; a < NINB; ++a) {
+      if (PG::COMPILED && a >= n_in_of<PG>(P)) break;
 #pragma unroll
       for (int e = 0; e < E; ++e) L[a][e] = ((vmask >> e) & 1) ? L[a][e] : (T)0;
+    }
   }
 }
 
@@ -280,13 +335,14 @@ __device__ __forceinline__ void vm_step(
     typename GVec<T, Shape<T, HV, SPMV, NR, ROWS>::GS>::type (&R3)[NR],
     VmState<T, Shape<T, HV, SPMV, NR, ROWS>::NG, Shape<T, HV, SPMV, NR, ROWS>::GS>& G,
     T (&L)[NINB][Shape<T, HV, SPMV, NR, ROWS>::E], int64_t row0, int64_t c0, unsigned vmask, const int mode,
-    const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval, const T* stl = nullptr, int q = 0) {
+    const bool pf_next, const int64_t next_row0, int32_t* scol, T* sval, const T* stl, int q, const int64_t cbase) {
   typedef Shape<T, HV, SPMV, NR, ROWS> S;
   constexpr bool HEAVY = S::HEAVY;
   constexpr int V = S::V, U = S::U, TW = S::TW, E = S::E, GS = S::GS, NG = S::NG;
   static_assert(NINB <= NR, "stream bucket exceeds the register file");
   typedef typename GVec<T, GS>::type gvec;
   typedef T vecA __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  const VmParams& Q = step_params<PG>(P);   // the stream descriptors
   // element e of a register lives in group e / GS, component e % GS
 #define RSET(a, e, x) { const int g_ = (e) / GS; \
     if (g_ == 0) gset<T, GS>(R0[a], (e) % GS, x); else if (g_ == 1) gset<T, GS>(R1[a], (e) % GS, x); \
@@ -298,7 +354,7 @@ __device__ __forceinline__ void vm_step(
     const int lane = threadIdx.x & (WAVE - 1);
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
-      if (a >= P.n_in) break;
+      if (a >= n_in_of<PG>(P)) break;
       if (PG::COMPILED ? PG::st_on[a] != 0 : P.st_on[a] != 0) {
         const int dr = PG::COMPILED ? PG::st_dr[a] : P.st_dr[a], dc = PG::COMPILED ? PG::st_dc[a] : P.st_dc[a];
         const T* src = stl + (q + dr) * PITCH + lane * V + dc;
@@ -307,10 +363,10 @@ __device__ __forceinline__ void vm_step(
 #pragma unroll
           for (int v = 0; v < V; ++v) RSET(a, u * V + v, src[u * PITCH + v]);
       } else {
-        const T* b = (const T*)P.in[a].base;
+        const T* b = (const T*)Q.in[a].base;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const vecA w = *(const vecA*)(b + (row0 + u) * P.in[a].s_row + c0);
+          const vecA w = *(const vecA*)(b + (row0 + u) * Q.in[a].s_row + c0);
 #pragma unroll
           for (int v = 0; v < V; ++v) RSET(a, u * V + v, w[v]);
         }
@@ -320,26 +376,41 @@ __device__ __forceinline__ void vm_step(
     // issued by the caller (or prefetched by the previous step) into L
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
-      if (a >= P.n_in) break;
+      if (a >= n_in_of<PG>(P)) break;
 #pragma unroll
       for (int e = 0; e < E; ++e) RSET(a, e, L[a][e]);
     }
-    if (pf_next) vm_load<T, V, U, E, NINB>(P, L, next_row0, c0, (1u << E) - 1, MODE_FAST);
+    if (pf_next) vm_load<T, V, U, E, NINB, PG>(P, L, next_row0, c0, (1u << E) - 1, MODE_FAST, cbase);
+  } else if (PG::COMPILED && mode == MODE_FAST) {
+    // a compiled pass's own streams, each row at its scalar base plus the
+    // lane's offset (cbase: the step's first column)
+    const uint32_t loff = (uint32_t)((threadIdx.x & (WAVE - 1)) * V * sizeof(T));
+#pragma unroll
+    for (int a = 0; a < NINB; ++a) {
+      if (a >= n_in_of<PG>(P)) break;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const vecA w = *(const vecA*)(row_base<T>(Q.in[a], row0 + u, cbase) + loff);
+#pragma unroll
+        for (int v = 0; v < V; ++v) RSET(a, u * V + v, w[v]);
+      }
+    }
   } else if (mode != MODE_SLOW) {
     // every stream of the bucket, padding slots from a zero page, in flight
-    // before the first wait
+    // before the first wait (a compiled pass loads its own streams only)
     T Ls[NINB][E];
     bool okv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) okv[u] = ((vmask >> (u * V)) & ((1u << V) - 1)) != 0;
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
-      const T* b = (const T*)P.in[a].base;
+      if (PG::COMPILED && a >= n_in_of<PG>(P)) break;
+      const T* b = (const T*)Q.in[a].base;
       // column stride is 1 for real streams and 0 for padding slots
-      const int64_t cc = c0 & (-P.in[a].s_col);
+      const int64_t cc = c0 & (-Q.in[a].s_col);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const T* p = b + (row0 + u) * P.in[a].s_row + cc;
+        const T* p = b + (row0 + u) * Q.in[a].s_row + cc;
         if (mode == MODE_CLAMP) p = okv[u] ? p : b;
         const vecA w = *(const vecA*)p;
 #pragma unroll
@@ -348,21 +419,25 @@ __device__ __forceinline__ void vm_step(
     }
     if (mode == MODE_CLAMP) {
 #pragma unroll
-      for (int a = 0; a < NINB; ++a)
+      for (int a = 0; a < NINB; ++a) {
+        if (PG::COMPILED && a >= n_in_of<PG>(P)) break;
 #pragma unroll
         for (int e = 0; e < E; ++e) Ls[a][e] = ((vmask >> e) & 1) ? Ls[a][e] : (T)0;
+      }
     }
 #pragma unroll
-    for (int a = 0; a < NINB; ++a)
+    for (int a = 0; a < NINB; ++a) {
+      if (PG::COMPILED && a >= n_in_of<PG>(P)) break;
 #pragma unroll
       for (int e = 0; e < E; ++e) RSET(a, e, Ls[a][e]);
+    }
   } else {
     // per-element masked loads, one stream at a time (a compiled pass
     // unrolls the streams, so its register indices stay constants)
 #define DFX_SLOW_LOAD(a)                                                 \
   {                                                                      \
-    const T* b = (const T*)P.in[a].base;                                 \
-    const int64_t sr = P.in[a].s_row, sc = P.in[a].s_col;                \
+    const T* b = (const T*)Q.in[a].base;                                 \
+    const int64_t sr = Q.in[a].s_row, sc = Q.in[a].s_col;                \
     gvec w[NG];                                                          \
     _Pragma("unroll") for (int e = 0; e < E; ++e) {                      \
       const int u = e / V, v = e % V;                                    \
@@ -383,12 +458,12 @@ __device__ __forceinline__ void vm_step(
         const int64_t row0 = row0x, c0 = c0x;
 #pragma unroll
         for (int a = 0; a < NINB; ++a) {
-          if (a >= P.n_in) break;
+          if (a >= n_in_of<PG>(P)) break;
           DFX_SLOW_LOAD(a)
         }
       }
     } else {
-      for (int a = 0; a < P.n_in; ++a) DFX_SLOW_LOAD(a)
+      for (int a = 0; a < n_in_of<PG>(P); ++a) DFX_SLOW_LOAD(a)
     }
 #undef DFX_SLOW_LOAD
   }
@@ -435,18 +510,21 @@ __device__ __forceinline__ void vm_step(
   if (mode != MODE_SLOW) {
 #pragma unroll
     for (int s = 0; s < VM_MAXOUT; ++s) {
-      if (s < P.n_out) {
+      if (s < n_out_of<PG>(P)) {
         const int o = PG::COMPILED ? PG::out_reg[s] : P.out_reg[s];
         gvec ev[NG];
         FOR_G(ev[g] = Rg[o];)
-        T* b = (T*)P.out[s].base;
-        const int64_t sr = P.out[s].s_row;
+        T* b = (T*)Q.out[s].base;
+        const int64_t sr = Q.out[s].s_row;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           vecA w;
 #pragma unroll
           for (int v = 0; v < V; ++v) w[v] = gget<T, GS>(ev[(u * V + v) / GS], (u * V + v) % GS);
-          if (mode == MODE_FAST) *(vecA*)(b + (row0 + u) * sr + c0) = w;
+          if (PG::COMPILED && mode == MODE_FAST)
+            *(vecA*)(row_base<T>(Q.out[s], row0 + u, cbase) + (uint32_t)((threadIdx.x & (WAVE - 1)) * V * sizeof(T))) =
+                w;
+          else if (mode == MODE_FAST) *(vecA*)(b + (row0 + u) * sr + c0) = w;
           else if ((vmask >> (u * V)) & 1) *(vecA*)(b + (row0 + u) * sr + c0) = w;
         }
       }
@@ -456,8 +534,8 @@ __device__ __forceinline__ void vm_step(
   {                                                                                            \
     gvec ev[NG];                                                                               \
     FOR_G(ev[g] = Rg[o];)                                                                      \
-    T* b = (T*)P.out[s].base;                                                                  \
-    const int64_t sr = P.out[s].s_row, sc = P.out[s].s_col;                                    \
+    T* b = (T*)Q.out[s].base;                                                                  \
+    const int64_t sr = Q.out[s].s_row, sc = Q.out[s].s_col;                                    \
     _Pragma("unroll") for (int q = 0; q < E; ++q) {                                            \
       const int u = q / V, v = q % V;                                                          \
       if ((vmask >> q) & 1) b[(row0 + u) * sr + (c0 + v) * sc] = gget<T, GS>(ev[q / GS], q % GS); \
@@ -471,12 +549,12 @@ __device__ __forceinline__ void vm_step(
         const int64_t row0 = row0x, c0 = c0x;
 #pragma unroll
         for (int s = 0; s < VM_MAXOUT; ++s) {
-          if (s >= P.n_out) break;
+          if (s >= n_out_of<PG>(P)) break;
           DFX_SLOW_STORE(s, PG::out_reg[s])
         }
       }
     } else {
-      for (int s = 0; s < P.n_out; ++s) {
+      for (int s = 0; s < n_out_of<PG>(P); ++s) {
         const int o = P.out_reg[s];
         DFX_SLOW_STORE(s, o)
       }
@@ -577,7 +655,7 @@ __device__ __forceinline__ void vm_stencil_tile(
       vm_step<T, HV, SPMV, NR, NINB, false, ROWS, false, true, PG>(P, R0, R1, R2, R3, G, L,
                                                                tr * RED_TH + (int64_t)c * ST_RCH + q, c0,
                                                                (1u << E) - 1, MODE_FAST, false, 0, nullptr, nullptr,
-                                                               cur, q);
+                                                               cur, q, cbase);
     if constexpr (ST_NBUF == 1)
       if (c + 1 < NCH) {
         __builtin_amdgcn_s_waitcnt(0);
@@ -720,34 +798,43 @@ void vm_kernel(const VmParams P) {
       if (staged) vm_stencil_tile<T, HV, SPMV, NR, NINB, ROWS, PG>(P, R0, R1, R2, R3, G, L, tr, cbase, c0, wib);
     }
     for (int r = r_lo; r < (staged ? r_lo : r_hi); r += U) {
+      // the step's bounds (a compiled pass reads them again at every step;
+      // the interpreter's are the kernel argument's, kept live)
+      const VmParams* CP = nullptr;
+      if constexpr (PG::COMPILED) CP = &step_params<PG>(P);
+#define DFX_C(f) (PG::COMPILED ? CP->f : P.f)
       const int64_t row0 = tr * RED_TH + r;
-      if (row0 >= P.rows) break;
-      const bool interior = P.is1d ? ((row0 + U) * TW <= P.n1d)
-                                   : (row0 + U <= P.rows && cbase >= 0 && cbase + TW <= P.cols);
+      if (row0 >= DFX_C(rows)) break;
+      const bool interior = DFX_C(is1d) ? ((row0 + U) * TW <= DFX_C(n1d))
+                                        : (row0 + U <= DFX_C(rows) && cbase >= 0 && cbase + TW <= DFX_C(cols));
       int mode = MODE_FAST;
       unsigned vmask = (1u << E) - 1;
-      if (!(P.unit_cols && interior)) {
-        mode = P.vec_cols ? MODE_CLAMP : MODE_SLOW;
+      if (!(DFX_C(unit_cols) && interior)) {
+        mode = DFX_C(vec_cols) ? MODE_CLAMP : MODE_SLOW;
         vmask = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const int64_t row = row0 + e / V, col = c0 + e % V;
-          const bool ok = P.is1d ? (row * TW + col < P.n1d) : (row < P.rows && col >= 0 && col < P.cols);
+          const bool ok = DFX_C(is1d) ? (row * TW + col < DFX_C(n1d))
+                                      : (row < DFX_C(rows) && col >= 0 && col < DFX_C(cols));
           vmask |= (ok ? 1u : 0u) << e;
         }
       }
       bool next_fast = false;
       if constexpr (SPLIT)
-        if (mode != MODE_SLOW && !(have && mode == MODE_FAST)) vm_load<T, V, U, E, NINB>(P, L, row0, c0, vmask, mode);
+        if (mode != MODE_SLOW && !(have && mode == MODE_FAST))
+          vm_load<T, V, U, E, NINB, PG>(P, L, row0, c0, vmask, mode, cbase);
       if constexpr (PF) {
         const int64_t nr = row0 + U;
-        next_fast = r + U < r_hi && P.unit_cols &&
-                    (P.is1d ? ((nr + U) * TW <= P.n1d) : (nr + U <= P.rows && cbase >= 0 && cbase + TW <= P.cols));
+        next_fast = r + U < r_hi && DFX_C(unit_cols) &&
+                    (DFX_C(is1d) ? ((nr + U) * TW <= DFX_C(n1d))
+                                 : (nr + U <= DFX_C(rows) && cbase >= 0 && cbase + TW <= DFX_C(cols)));
       }
       if constexpr (PG::COMPILED) G.drow = r;
       vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS, false, false, PG>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode,
                                                                     next_fast, row0 + U, sp_col[SPMV ? wib : 0],
-                                                                    sp_val[SPMV ? wib : 0]);
+                                                                    sp_val[SPMV ? wib : 0], nullptr, 0, cbase);
+#undef DFX_C
       have = next_fast;
     }
     // ---- tile sums into the block's LDS row ---------------------------------------
