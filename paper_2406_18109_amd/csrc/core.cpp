@@ -1350,14 +1350,22 @@ static int col_shift_for(const PassPlan& p, const VmParams& P, size_t es) {
 // of the GMG fine level ran 256 waves); splitting a tile's rows over several
 // waves changes no bit when nothing is reduced.  The split aims at about
 // 8192 waves per pass, down to one row per wave for SpMV passes (one row
-// per step) and two otherwise (two-row steps).  Stencil-staged passes stage
-// whole tiles and keep one wave.  DFX_ROW_SPLIT=<n> caps it (0 or 1: off).
+// per step) and two otherwise (two-row steps); transcendental passes aim at
+// 32768.  Stencil-staged passes stage whole tiles and keep one wave.
+// DFX_ROW_SPLIT=<n> caps it (0 or 1: off), DFX_SPLIT_WAVES=<n> sets the aim.
 static int row_split_for(const PassPlan& p, const VmParams& P) {
   int cap = p.kind == 1 ? RED_TH : RED_TH / 2;
   if (const char* e = std::getenv("DFX_ROW_SPLIT")) cap = std::max(1, std::min(cap, std::atoi(e)));
   if (P.n_red != 0 || P.st_n != 0 || P.tiles_per_wave != 1 || p.kind == 2) return 1;
+  // waves per pass to aim at: transcendental passes keep the VALU busy and
+  // gain from a finer tail (Black-Scholes FP32 over 2^26 options, 8192
+  // tiles: 0.383 ms at 8192 waves, 0.372 at 16384, 0.359 at 32768); streaming
+  // passes lose from the extra waves (the COPY pass: 0.208 ms at 8192, 0.218
+  // at 32768)
+  int64_t target = p.tier != TIER_ARITH ? 32768 : 8192;
+  if (const char* e = std::getenv("DFX_SPLIT_WAVES")) target = std::max<int64_t>(1, std::atoll(e));
   int s = 1;
-  while (2 * s <= cap && P.n_tiles * 2 * s <= 8192) s *= 2;
+  while (2 * s <= cap && P.n_tiles * 2 * s <= target) s *= 2;
   // a lone tile of one row has work for one wave only
   if (P.n_tiles == 1 && p.rows <= 1) s = 1;
   return s;
