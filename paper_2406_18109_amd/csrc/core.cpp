@@ -92,8 +92,23 @@ static void* dev_alloc(Ctx& c, size_t bytes) {
   return p;
 }
 
+// Reduce the block sums that wait for a consumer pass (run_pass) with the
+// block-sum kernel.  Called at the end of every flush and before the memory
+// that holds the block sums or their results is returned.
+static int launch_pending_final(Ctx& c) {
+  if (!c.fin_pending) return 0;
+  c.fin_pending = false;
+  return launch_vm_final(c.fin, c.fin_f64, c.stream);
+}
+
 static void dev_free(Ctx& c, void* p, size_t bytes) {
   if (!p) return;
+  if (c.fin_pending) {
+    // (partials[0] is the start of the pass's workspace)
+    bool mine = p == c.fin.partials[0];
+    for (int k = 0; k < c.fin.n_red; ++k) mine = mine || p == c.fin.result[k];
+    if (mine) (void)launch_pending_final(c);   // (a launch error reappears at the next launch)
+  }
   if (c.no_alloc) {   // returned at the next call that may free
     c.deferred_free.emplace_back(p, bytes);
     return;
@@ -1206,6 +1221,10 @@ static int build_plan(Ctx& c, int f, const std::set<int64_t>& temps, const std::
     PassPlan pp;
     int rc = lower_pass(c, L, g.tasks, g.sp, g.dtype, g.kind, pp);
     if (rc) return rc;
+    // a pass that stores nothing (every value it computes is a temporary
+    // nobody reads, as the residual of a Jacobi sweep whose program has
+    // already dropped it) has no effect and is not launched
+    if (pp.outs.empty() && pp.red_cstore.empty()) continue;
     plan.alg_bytes += pp.alg_bytes;
     plan.passes.push_back(std::move(pp));
   }
@@ -1420,6 +1439,19 @@ static int staged_streams(const PassPlan& p, size_t n_stores) {
   return n;
 }
 
+// Does the pass name one of the stores in `ids` (as input, output,
+// broadcast, reduction or SpMV operand)?
+static bool pass_touches(const PassPlan& p, const std::vector<int64_t>& order, const std::vector<int64_t>& ids) {
+  auto hit = [&](int cs) { return cs >= 0 && std::find(ids.begin(), ids.end(), order[cs]) != ids.end(); };
+  for (auto& s : p.ins) if (hit(s.cstore)) return true;
+  for (auto& s : p.outs) if (hit(s.cstore)) return true;
+  for (int cs : p.bc_cstore) if (hit(cs)) return true;
+  for (int cs : p.red_cstore) if (hit(cs)) return true;
+  if (p.kind == 1)
+    for (int cs : {p.spmv_rowptr, p.spmv_col, p.spmv_val, p.spmv_x}) if (hit(cs)) return true;
+  return false;
+}
+
 static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   auto S = [&](int cs) -> StoreRec& { return c.stores.at(order[cs]); };
   const size_t es = dtype_size(p.dtype);
@@ -1622,9 +1654,30 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.grid = (int)p.n_tiles;
     F.nblocks = (int)p.n_tiles;
   }
+  // Block sums an earlier pass left waiting: a compiled one-block pass of
+  // the same element type reduces them first, in its own launch (the same
+  // tree as the block-sum kernel); a pass that reduces (its block sums may
+  // share the allocation-free scratch) or names one of their result stores
+  // has them reduced by the block-sum kernel before it; any other pass runs
+  // with them still waiting (it reads none of their stores).
+  // DFX_FIN_ATTACH=0 turns the attachment off.
+  int e = 0;
+  if (c.fin_pending) {
+    const char* fa = std::getenv("DFX_FIN_ATTACH");
+    const bool fin_attach = !(fa && fa[0] == '0');
+    if (fin_attach && fn && P.grid == 1 && c.fin_f64 == (p.dtype == DFX_F64 ? 1 : 0) &&
+        c.fin.nblocks <= FIN_MAX_CHUNKS * FINAL_CHUNK) {
+      P.fin = c.fin;
+      c.fin_pending = false;
+      c.stats.launches -= 1;
+      if (c.capturing) c.capture_launches -= 1;
+    } else if (P.n_red > 0 || pass_touches(p, order, c.fin_stores)) {
+      e = launch_pending_final(c);
+    }
+  }
   if (timed) (void)hipEventRecord(p.ev0, c.stream);
-  int e;
-  if (fn) {
+  if (e != 0) {
+  } else if (fn) {
     const JitVariant v = jit_variant(p.dtype == DFX_F64, p.tier, P.n_in, P.spmv, P.st_n, rows);
     void* args[] = {(void*)&P};
     e = (int)hipModuleLaunchKernel(fn, (unsigned)P.grid, 1, 1, BLOCK, 1, 1, (unsigned)vm_dyn_lds_bytes(P, v.sten != 0),
@@ -1634,7 +1687,14 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   } else {
     e = launch_vm(P, p.dtype == DFX_F64, p.tier, rows, c.stream);
   }
-  if (e == 0 && F.n_red > 0 && !P.red_direct) e = launch_vm_final(F, p.dtype == DFX_F64, c.stream);
+  if (e == 0 && F.n_red > 0 && !P.red_direct) {
+    // its block sums wait for the next pass (above), or for the window's end
+    c.fin_pending = true;
+    c.fin = F;
+    c.fin_f64 = p.dtype == DFX_F64 ? 1 : 0;
+    c.fin_stores.clear();
+    for (int cs : p.red_cstore) c.fin_stores.push_back(order[cs]);
+  }
   if (timed) (void)hipEventRecord(p.ev1, c.stream);
   if (e != 0) return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
@@ -1774,6 +1834,8 @@ static int flush(Ctx& c) {
     int rc = dispatch_one(c);
     if (rc) return rc;
   }
+  if (const int e = launch_pending_final(c))
+    return fail(c, DFX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)e));
   return DFX_OK;
 }
 

@@ -170,6 +170,13 @@ struct Ctx {
 
   bool capturing = false;
   int64_t capture_launches = 0, capture_bytes = 0, capture_compiled = 0;
+  // Block sums of the last reducing pass not yet reduced (run_pass): the
+  // next compiled one-block pass reduces them in its prologue instead of a
+  // block-sum kernel launch; launched at the latest when the window ends.
+  bool fin_pending = false;
+  VmFinal fin{};
+  int fin_f64 = 0;
+  std::vector<int64_t> fin_stores;   // its 0-d result stores
   std::vector<std::unique_ptr<Graph>> graphs;
 
   dfx_stats stats{};

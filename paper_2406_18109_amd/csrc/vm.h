@@ -113,6 +113,19 @@ struct VmStream {
   int64_t s_row, s_col; // element strides
 };
 
+// The block-sum kernel: reduces `nblocks` block sums per reduction and stores
+// (init) or accumulates into the 0-d result.
+struct VmFinal {
+  int32_t n_red, nblocks;
+  const void* partials[VM_MAXRED];
+  void* result[VM_MAXRED];
+  int32_t init[VM_MAXRED];
+};
+
+// Block sums a one-block compiled pass reduces before its own work (an
+// earlier pass's VmFinal), at most FIN_MAX_CHUNKS chunks of FINAL_CHUNK.
+constexpr int FIN_MAX_CHUNKS = 64;
+
 struct VmParams {
   int32_t n_code, n_in, n_out, n_bc, n_red;
   int32_t is1d;         // 1: space of n1d elements cut into rows of TW
@@ -169,6 +182,10 @@ struct VmParams {
   int8_t st_on[VM_MAXIN], st_dr[VM_MAXIN], st_dc[VM_MAXIN];
   const void* st_base;
   int64_t st_srow, st_lim;
+  // (compiled one-block passes) an earlier pass's block sums to reduce into
+  // its 0-d results first, with the block-sum kernel's tree (fin.n_red 0:
+  // none); the host attaches it in place of that kernel's launch
+  VmFinal fin;
   VmInstr code[VM_MAXCODE + 1];    // one spare entry: the kernel prefetches code[pc + 1]
 };
 
@@ -188,14 +205,5 @@ inline size_t vm_dyn_lds_bytes(const VmParams& P, bool sten) {
 // slot instead of the plan's workspace.
 constexpr int NOALLOC_BLOCKS = 16384;
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)NOALLOC_BLOCKS * VM_MAXRED * 8;
-
-// The block-sum kernel: reduces `nblocks` block sums per reduction and stores
-// (init) or accumulates into the 0-d result.
-struct VmFinal {
-  int32_t n_red, nblocks;
-  const void* partials[VM_MAXRED];
-  void* result[VM_MAXRED];
-  int32_t init[VM_MAXRED];
-};
 
 }  // namespace dfx

@@ -585,6 +585,53 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
   return v;
 }
 
+// The block-sum kernel's reduction (vm_final) evaluated by one block of
+// BLOCK threads at the start of a compiled one-block pass: for each chunk of
+// FINAL_CHUNK block sums, wave w reduces the aligned quarter [256w, 256w +
+// 256) with block_tree and the quarter sums are combined as the two top
+// levels of the chunk's tree; then wave k reduces reduction k's chunk sums
+// with block_tree.  Every addition pairs the same operands as vm_final's
+// level-by-level tree, so the results have its bits.
+template <typename T> __device__ __forceinline__ void fin_sums(const VmFinal& F) {
+  static_assert(FINAL_CHUNK == BLOCK * 4 && BLOCK / WAVE == 4, "four waves of 256 sums per chunk");
+  __shared__ T fcs[VM_MAXRED][FIN_MAX_CHUNKS];
+  __shared__ T fws[VM_MAXRED][BLOCK / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int nch = (F.nblocks + FINAL_CHUNK - 1) / FINAL_CHUNK;
+  for (int c = 0; c < nch; ++c) {
+    const int L = min(FINAL_CHUNK, F.nblocks - c * FINAL_CHUNK);
+    const int cnt = min(max(L - w * 4 * WAVE, 0), 4 * WAVE);
+#pragma unroll
+    for (int k = 0; k < VM_MAXRED; ++k) {
+      if (k < F.n_red) {
+        const T* a = (const T*)F.partials[k] + (int64_t)c * FINAL_CHUNK + w * 4 * WAVE;
+        const T v = cnt > 0 ? block_tree(a, cnt, lane) : (T)0;
+        if (lane == 0) fws[k][w] = v;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < F.n_red) {
+      const int k = threadIdx.x;
+      T a = fws[k][0], b = fws[k][2];
+      if (4 * WAVE < L) a = a + fws[k][1];
+      if (12 * WAVE < L) b = b + fws[k][3];
+      if (8 * WAVE < L) a = a + b;
+      fcs[k][c] = a;
+    }
+    __syncthreads();
+  }
+  if (w < F.n_red) {
+    const T total = nch > 0 ? block_tree(fcs[w], nch, lane) : (T)0;
+    if (lane == 0) {
+      // (a vector load: the scalar cache must not keep the old value, which
+      // the pass may read again after this store)
+      T* res = (T*)F.result[w];
+      *res = F.init[w] ? total : *(volatile T*)res + total;
+    }
+  }
+}
+
 // Stencil staging: an interior tile of a pass whose input streams include
 // shifted views of one store (the stencil of section 2: five offset views of
 // one grid).  The tile's rows are processed in chunks of ST_RCH; for each
@@ -683,6 +730,15 @@ void vm_kernel(const VmParams P) {
   // SpMV kernels: per wave, the staged CSR range of one 64-row group
   __shared__ int32_t sp_col[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
   __shared__ T sp_val[SPMV ? BLOCK / WAVE : 1][SPMV ? SP_CAP : 1];
+
+  // a compiled one-block pass first reduces an earlier pass's block sums
+  // (P.fin), in place of the block-sum kernel's launch
+  if constexpr (PG::COMPILED) {
+    if (P.fin.n_red > 0) {
+      fin_sums<T>(P.fin);
+      __syncthreads();
+    }
+  }
 
   // One-tile SpMV passes (sp_coop, one block): the block's four waves first
   // compute the tile's rows, four 64-row groups per lane at once, into

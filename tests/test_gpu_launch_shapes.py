@@ -1,10 +1,12 @@
 """Launch shapes that must not change a bit, each against its own switch:
 row_split (waves per tile of passes without reductions), col_shift (strips
-started early so that views misaligned alike access aligned vectors) and
+started early so that views misaligned alike access aligned vectors),
 red_split (compiled passes with one reduction: a block of four waves per
-tile, summands added in the canonical order).  Every workload runs with the
-shape on and with it off and must give identical results; the misaligned
-views are also checked against numpy."""
+tile, summands added in the canonical order) and fin_attach (a compiled
+one-block pass reduces the block sums an earlier pass left, in place of the
+block-sum kernel).  Every workload runs with the shape on and with it off
+and must give identical results; the misaligned views are also checked
+against numpy."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ from test_gpu_parity import cg_gpu, jacobi_gpu
 
 pytestmark = pytest.mark.gpu
 
-SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT")
+SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT", "DFX_FIN_ATTACH")
 
 
 def _runs(monkeypatch, fn, jit):
@@ -105,3 +107,50 @@ def test_misaligned_views(monkeypatch, dtype, cols, off):
     ey[r0:r0 + h, c0:c0 + w] = sa + sb * npdt(2.0)
     ez[r0:r0 + h, c0:c0 + w] = sa * sb
     assert np.array_equal(y, ey) and np.array_equal(z, ez)
+
+
+@pytest.mark.parametrize("dtype,n", [("f64", (1 << 25) + 3 * 4096 + 77), ("f32", (1 << 24) + 5), ("f64", 70000)])
+def test_fin_attach_many_blocks(monkeypatch, dtype, n):
+    """A reduction over thousands of blocks (several chunks of block sums,
+    the last one ragged), then a one-element task that reads its result and
+    one that does not: with every pass compiled, the one-element pass reduces
+    the block sums itself (one launch fewer) and every bit stays the same."""
+    note("shapes fin attach %s n=%d" % (dtype, n))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    x = synth.uniform(7, 3, n, -1.0, 1.0).astype(npdt)
+
+    def run(attach):
+        monkeypatch.setenv("DFX_JIT", "2")
+        if attach:
+            monkeypatch.delenv("DFX_FIN_ATTACH", raising=False)
+        else:
+            monkeypatch.setenv("DFX_FIN_ATTACH", "0")
+        try:
+            c = dfx.Context(device=0, window_size=8, tune=False)
+            hx = upload(c, x)
+            N, T = c.part_none(), c.part_tiling([n])
+            out = []
+            for rep in range(2):   # the second round runs the memoised, compiled plans
+                ss = c.store_create([], dtype)
+                c.submit("sumsq", [1], [(hx, T, "R"), (ss, N, "Rd")], (1,))
+                two = c.store_create([], dtype)
+                c.submit("sqrt", [], [(ss, N, "R"), (two, N, "W")])
+                c.flush()
+                c.stats_reset()
+                c.submit("sumsq", [1], [(hx, T, "R"), (ss, N, "Rd")], (1,))
+                c.submit("sqrt", [], [(ss, N, "R"), (two, N, "W")])
+                c.flush()
+                out.append((c.store_read(ss, [], dtype), c.store_read(two, [], dtype), c.stats()["launches"]))
+                c.store_release(ss)
+                c.store_release(two)
+            c.close()
+            return out[-1]
+        finally:
+            monkeypatch.delenv("DFX_JIT", raising=False)
+            monkeypatch.delenv("DFX_FIN_ATTACH", raising=False)
+    a_ss, a_r, a_l = run(True)
+    b_ss, b_r, b_l = run(False)
+    assert np.array_equal(a_ss, b_ss) and np.array_equal(a_r, b_r)
+    assert a_l == b_l - 1, (a_l, b_l)
+    ref = float(np.sum(x.astype(np.float64) ** 2))
+    assert abs(float(a_ss) - ref) <= (1e-10 if dtype == "f64" else 1e-4) * ref
