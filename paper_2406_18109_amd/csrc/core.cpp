@@ -1363,6 +1363,44 @@ static int col_shift_for(const PassPlan& p, const VmParams& P, size_t es) {
   return mis > 0 ? (int)mis : 0;
 }
 
+// Realigned inputs (compiled passes): a 2-D pass without reductions whose
+// outputs share a misalignment m (elements past a 16-byte word, 0 < m < V)
+// while some input has another one.  Shifting the strips by m aligns every
+// output vector; input a then starts d_a = (m_a - m) mod V elements past a
+// word, and the compiled kernel loads it with aligned vectors and a lane
+// shift (realigned_row).  The Jacobi sweep's copy from an aligned array into
+// the grid interior is the case.  Returns m and fills d (0: not this case).
+// DFX_REALIGN=0 turns it off.
+static int realign_for(const PassPlan& p, const VmParams& P, size_t es, std::vector<int8_t>& d) {
+  d.clear();
+  const char* e = std::getenv("DFX_REALIGN");
+  if (e && e[0] == '0') return 0;
+  if (p.kind != 0 || p.is1d || P.n_red != 0 || P.st_n != 0 || !p.unit_cols || P.n_out == 0) return 0;
+  const int64_t V = 16 / (int64_t)es;
+  auto mis = [&](const VmStream& st) -> int64_t {
+    const uintptr_t a = (uintptr_t)st.base;
+    if (a % es != 0 || st.s_row % V != 0 || st.s_col != 1) return -1;
+    return (int64_t)((a / es) % (uintptr_t)V);
+  };
+  int64_t m = -1;
+  for (int k = 0; k < P.n_out; ++k) {
+    const int64_t mk = mis(P.out[k]);
+    if (mk < 0 || (m >= 0 && mk != m)) return 0;
+    m = mk;
+  }
+  if (m <= 0) return 0;
+  bool any = false;
+  for (int k = 0; k < P.n_in; ++k) {
+    const int64_t mk = mis(P.in[k]);
+    if (mk < 0) { d.clear(); return 0; }
+    const int8_t dk = (int8_t)(((mk - m) % V + V) % V);
+    d.push_back(dk);
+    any = any || dk != 0;
+  }
+  if (!any) d.clear();
+  return any ? (int)m : 0;
+}
+
 // Waves per tile of a pass without reductions (a power of two up to 32).
 // With one wave per tile a pass of few tiles leaves most of the chip idle
 // and each wave walks its tile's 32 rows in sequence (the 256-tile passes
@@ -1413,6 +1451,7 @@ static std::shared_ptr<JitEntry> request_compiled(PassPlan& p, int st_n, int row
   JitProgram g;
   g.n_in = (int)p.ins.size();
   g.n_out = (int)p.outs.size();
+  for (int8_t d : p.realign) g.realign.push_back(d);
   g.code = p.code;
   g.out_reg = p.out_reg;
   g.bc_reg = p.bc_reg;
@@ -1620,9 +1659,26 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   P.row_split = 1;
   P.col_shift = 0;
   if (c.batch_rec) return batch_record_pass(c, P, F, p.dtype, p.tier);
+  const int rows = pick_rows(c, p);
+  // compiled kernel, once ready (module loading is kept out of captures);
+  // a pass with realigned inputs compiles them in (see realign_for) and runs
+  // its kernel only while its streams keep those alignments
+  hipFunction_t fn = nullptr;
+  std::vector<int8_t> ra;
+  const int ra_shift = c.cfg.jit ? realign_for(p, P, es, ra) : 0;
+  if (c.cfg.jit) {
+    if (!p.jit_checked) {
+      p.jit_checked = true;
+      p.realign = ra;
+      p.realign_shift = ra_shift;
+      if (jit_wanted(p, P.st_n) || ra_shift > 0) p.jit = request_compiled(p, P.st_n, rows, c.cfg.jit == 2);
+    }
+    if (p.jit && ra == p.realign) fn = jit_function(*p.jit, c.cfg.device, !c.capturing);
+  }
   // column shift (aligned output vectors), then row split, of passes
   // without reductions; either changes the launch shape only
-  if (const int cs = col_shift_for(p, P, es); cs > 0) {
+  const int cs_shift = fn && ra_shift > 0 ? ra_shift : col_shift_for(p, P, es);
+  if (const int cs = cs_shift; cs > 0) {
     const int64_t TWp = p.dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW;
     const int64_t row_tiles = p.n_tiles / std::max<int64_t>(1, p.strips);
     P.col_shift = cs;
@@ -1635,16 +1691,6 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
     P.row_split = rs;
     P.sp_coop = 0;
     P.grid = grid_for(P.n_tiles * rs);
-  }
-  const int rows = pick_rows(c, p);
-  // compiled kernel, once ready (module loading is kept out of captures)
-  hipFunction_t fn = nullptr;
-  if (c.cfg.jit) {
-    if (!p.jit_checked) {
-      p.jit_checked = true;
-      if (jit_wanted(p, P.st_n)) p.jit = request_compiled(p, P.st_n, rows, c.cfg.jit == 2);
-    }
-    if (p.jit) fn = jit_function(*p.jit, c.cfg.device, !c.capturing);
   }
   // a compiled pass of one reduction and few tiles gives each tile a block
   // of four waves (red_split; bit-identical tile sums)

@@ -113,6 +113,10 @@ struct PassPlan {
   int st_cs = -1;
   int64_t st_off0 = 0, st_srow = 0;   // window origin (element offset) and row stride
   std::vector<int8_t> st_on, st_dr, st_dc;
+  // realigned inputs of the compiled kernel (run_pass): the strip shift
+  // that aligns the outputs and, per input, its elements past alignment
+  int realign_shift = 0;
+  std::vector<int8_t> realign;
   std::vector<VmInstr> code;
   std::vector<double> imm;
   int64_t alg_bytes = 0;

@@ -320,6 +320,10 @@ std::string jit_source(const JitVariant& v, const JitProgram& g, std::string* na
   s += "  static constexpr int st_on[VM_MAXIN] = " + int_list(g.st_on, VM_MAXIN) + ";\n";
   s += "  static constexpr int st_dr[VM_MAXIN] = " + int_list(g.st_dr, VM_MAXIN) + ";\n";
   s += "  static constexpr int st_dc[VM_MAXIN] = " + int_list(g.st_dc, VM_MAXIN) + ";\n";
+  bool any_realign = false;
+  for (int32_t d : g.realign) any_realign = any_realign || d != 0;
+  s += std::string("  static constexpr bool REALIGN = ") + (any_realign ? "true" : "false") + ";\n";
+  s += "  static constexpr int realign[VM_MAXIN] = " + int_list(g.realign, VM_MAXIN) + ";\n";
   s += "  template <typename T, int HV, int NR, int NG, int GS, int E>\n";
   s += "  static __device__ __forceinline__ void run(typename GVec<T, GS>::type (&R0)[NR],\n"
        "                                             typename GVec<T, GS>::type (&R1)[NR],\n"

@@ -47,6 +47,7 @@ struct JitProgram {
   std::vector<VmInstr> code;
   std::vector<int32_t> out_reg, bc_reg;
   std::vector<int32_t> st_on, st_dr, st_dc;   // stencil staging map (empty: none)
+  std::vector<int32_t> realign;   // per input: elements past alignment after the strip shift (empty: none)
 };
 
 struct JitEntry;

@@ -8,6 +8,7 @@
 
 #include "dev_common.h"
 #include "vm.h"
+#include "vm_exec.h"
 
 namespace dfx {
 
@@ -17,39 +18,9 @@ int launch_vm_tier1(const VmParams& P, int is_f64, int nb, hipStream_t stream);
 int launch_vm_tier2(const VmParams& P, int is_f64, int nb, hipStream_t stream);
 int launch_vm_tier3(const VmParams& P, int is_f64, int nb, hipStream_t stream);
 
-// Block sums -> 0-d results: chunks of FINAL_CHUNK block sums (complete
-// subtrees except the last) are reduced level by level in LDS, then the chunk
-// sums the same way.  All reductions of the pass advance together.
+// Block sums -> 0-d results (fin_sums: the canonical tree, 16 waves).
 template <typename T> __global__ __launch_bounds__(FINAL_BLOCK) void vm_final(const VmFinal F) {
-  __shared__ T sh[VM_MAXRED][FINAL_CHUNK];
-  __shared__ T cs[VM_MAXRED][FINAL_CHUNK];
-  const int tid = threadIdx.x;
-  const int nch = (F.nblocks + FINAL_CHUNK - 1) / FINAL_CHUNK;
-  for (int c = 0; c < nch; ++c) {
-    const int L = min(FINAL_CHUNK, F.nblocks - c * FINAL_CHUNK);
-    for (int k = 0; k < F.n_red; ++k)
-      sh[k][tid] = tid < L ? __builtin_nontemporal_load((const T*)F.partials[k] + (int64_t)c * FINAL_CHUNK + tid) : (T)0;
-    __syncthreads();
-    for (int h = 1; h < L; h <<= 1) {
-      const int i = tid * 2 * h;
-      if (i + h < L)
-        for (int k = 0; k < F.n_red; ++k) sh[k][i] = sh[k][i] + sh[k][i + h];
-      __syncthreads();
-    }
-    if (tid < F.n_red) cs[tid][c] = sh[tid][0];
-    __syncthreads();
-  }
-  for (int h = 1; h < nch; h <<= 1) {
-    const int i = tid * 2 * h;
-    if (i + h < nch)
-      for (int k = 0; k < F.n_red; ++k) cs[k][i] = cs[k][i] + cs[k][i + h];
-    __syncthreads();
-  }
-  if (tid < F.n_red) {
-    const T total = nch > 0 ? cs[tid][0] : (T)0;
-    T* res = (T*)F.result[tid];
-    *res = F.init[tid] ? total : *res + total;
-  }
+  fin_sums<T, FINAL_BLOCK / WAVE, FINAL_CHUNK>(F);
 }
 
 template __global__ void vm_final<double>(const VmFinal);

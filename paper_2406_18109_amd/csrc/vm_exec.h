@@ -180,6 +180,11 @@ struct VmInterp {
   static constexpr int out_reg[VM_MAXOUT] = {};
   static constexpr int bc_reg[VM_MAXBC] = {};
   static constexpr int st_on[VM_MAXIN] = {}, st_dr[VM_MAXIN] = {}, st_dc[VM_MAXIN] = {};
+  // (compiled passes) input a's vectors start realign[a] elements past an
+  // aligned address once the strips are shifted for the outputs; REALIGN:
+  // some do
+  static constexpr bool REALIGN = false;
+  static constexpr int realign[VM_MAXIN] = {};
   template <typename T, int HV, int NR, int NG, int GS, int E>
   static __device__ __forceinline__ void run(typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
                                              typename GVec<T, GS>::type (&)[NR], typename GVec<T, GS>::type (&)[NR],
@@ -246,6 +251,39 @@ __device__ __forceinline__ const char* row_base(const VmStream& s, int64_t row, 
   return (const char*)s.base + (row * s.s_row + cbase) * (int64_t)sizeof(T);
 }
 
+// Lane l's V elements of a row whose vectors start d (0 < d < V) elements
+// past an aligned address: the lane loads the aligned vector that holds its
+// first element (rb: the address of the step's first column minus d, plus
+// the lane's offset loff) and takes the rest from the next lane's through a
+// wave shift (DPP wave_shl: lane l reads lane l + 1); the last lane loads
+// the aligned vector after the strip itself.  Aligned loads instead of
+// vectors that straddle two 16-byte words.
+template <typename T> __device__ __forceinline__ T lane_next(const T x) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x130, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
+  }
+}
+// The loads (issued for every realigned row of a step before any is
+// combined, so that they are all in flight together) ...
+template <typename T, int V, typename VA>
+__device__ __forceinline__ void realign_load(const char* rb, const uint32_t loff, VA& w, VA& nx) {
+  w = *(const VA*)(rb + loff);
+  nx = VA{};
+  if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) nx = *(const VA*)(rb + loff + V * sizeof(T));
+}
+// ... and the lane's elements from them.
+template <typename T, int V, typename VA>
+__device__ __forceinline__ T realign_elem(const VA& w, const VA& nx, const int d, const int v) {
+  if (v < V - d) return w[v + d];
+  const T t = lane_next(w[v - (V - d)]);
+  return (threadIdx.x & (WAVE - 1)) == WAVE - 1 ? nx[v - (V - d)] : t;
+}
+
 // Input and output streams of a pass (compile-time for compiled passes).
 template <class PG> __device__ __forceinline__ int n_in_of(const VmParams& P) {
   return PG::COMPILED ? PG::N_IN : P.n_in;
@@ -267,14 +305,30 @@ __device__ __forceinline__ void vm_load(const VmParams& P, T (&L)[NINB][E], int6
     if (mode == MODE_FAST) {
       // (cbase: the step's first column, c0 - lane * V)
       const uint32_t loff = (uint32_t)((threadIdx.x & (WAVE - 1)) * V * sizeof(T));
+      vecA RW[PG::REALIGN ? NINB : 1][U], RN[PG::REALIGN ? NINB : 1][U];   // realigned rows
 #pragma unroll
       for (int a = 0; a < NINB; ++a) {
         if (a >= n_in_of<PG>(P)) break;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+          if (PG::realign[a] > 0) {
+            realign_load<T, V>(row_base<T>(Q.in[a], row0 + u, cbase - PG::realign[a]), loff, RW[a][u], RN[a][u]);
+            continue;
+          }
           const vecA w = *(const vecA*)(row_base<T>(Q.in[a], row0 + u, cbase) + loff);
 #pragma unroll
           for (int v = 0; v < V; ++v) L[a][u * V + v] = w[v];
+        }
+      }
+      if constexpr (PG::REALIGN) {
+#pragma unroll
+        for (int a = 0; a < NINB; ++a) {
+          if (a >= n_in_of<PG>(P)) break;
+          if (PG::realign[a] > 0)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int v = 0; v < V; ++v) L[a][u * V + v] = realign_elem<T, V>(RW[a][u], RN[a][u], PG::realign[a], v);
         }
       }
       return;
@@ -385,14 +439,30 @@ __device__ __forceinline__ void vm_step(
     // a compiled pass's own streams, each row at its scalar base plus the
     // lane's offset (cbase: the step's first column)
     const uint32_t loff = (uint32_t)((threadIdx.x & (WAVE - 1)) * V * sizeof(T));
+    vecA RW[PG::REALIGN ? NINB : 1][U], RN[PG::REALIGN ? NINB : 1][U];   // realigned rows
 #pragma unroll
     for (int a = 0; a < NINB; ++a) {
       if (a >= n_in_of<PG>(P)) break;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (PG::realign[a] > 0) {
+          realign_load<T, V>(row_base<T>(Q.in[a], row0 + u, cbase - PG::realign[a]), loff, RW[a][u], RN[a][u]);
+          continue;
+        }
         const vecA w = *(const vecA*)(row_base<T>(Q.in[a], row0 + u, cbase) + loff);
 #pragma unroll
         for (int v = 0; v < V; ++v) RSET(a, u * V + v, w[v]);
+      }
+    }
+    if constexpr (PG::REALIGN) {
+#pragma unroll
+      for (int a = 0; a < NINB; ++a) {
+        if (a >= n_in_of<PG>(P)) break;
+        if (PG::realign[a] > 0)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) RSET(a, u * V + v, (realign_elem<T, V>(RW[a][u], RN[a][u], PG::realign[a], v)));
       }
     }
   } else if (mode != MODE_SLOW) {
@@ -585,50 +655,79 @@ template <typename T> __device__ __forceinline__ T block_tree(const T* a, int cn
   return v;
 }
 
-// The block-sum kernel's reduction (vm_final) evaluated by one block of
-// BLOCK threads at the start of a compiled one-block pass: for each chunk of
-// FINAL_CHUNK block sums, wave w reduces the aligned quarter [256w, 256w +
-// 256) with block_tree and the quarter sums are combined as the two top
-// levels of the chunk's tree; then wave k reduces reduction k's chunk sums
-// with block_tree.  Every addition pairs the same operands as vm_final's
-// level-by-level tree, so the results have its bits.
-template <typename T> __device__ __forceinline__ void fin_sums(const VmFinal& F) {
-  static_assert(FINAL_CHUNK == BLOCK * 4 && BLOCK / WAVE == 4, "four waves of 256 sums per chunk");
-  __shared__ T fcs[VM_MAXRED][FIN_MAX_CHUNKS];
-  __shared__ T fws[VM_MAXRED][BLOCK / WAVE];
+// The block-sum reduction: one block of NW waves reduces F.nblocks block
+// sums per reduction (at most MAXCH chunks of FINAL_CHUNK) into the 0-d
+// results.  The tree is the canonical one: chunks of FINAL_CHUNK block sums
+// are complete subtrees (the last one ragged), then the chunk sums form the
+// same tree.  Within a chunk, wave q of a group of four reduces the aligned
+// quarter [256q, 256q + 256) with block_tree, and the quarter sums combine
+// as the chunk tree's two top levels; each round reduces NW / 4 chunks.  The
+// chunk sums take block_tree again (by quarters when there are more than
+// 256).  Every addition pairs the operands of the level-by-level pairwise
+// tree, so any NW gives the same bits.  The block-sum kernel runs it with
+// 16 waves; a compiled one-block pass runs it with its 4 before its own work.
+template <typename T, int NW, int MAXCH> __device__ __forceinline__ void fin_sums(const VmFinal& F) {
+  static_assert(FINAL_CHUNK == 16 * WAVE && NW % 4 == 0, "four waves of 256 sums per chunk");
+  static_assert(MAXCH <= 4 * WAVE || NW >= 4 * VM_MAXRED, "chunk sums by quarters need four waves per reduction");
+  constexpr int CPR = NW / 4;   // chunks per round
+  __shared__ T fcs[VM_MAXRED][MAXCH];
+  __shared__ T fws[VM_MAXRED][NW];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int q = w % 4;
   const int nch = (F.nblocks + FINAL_CHUNK - 1) / FINAL_CHUNK;
-  for (int c = 0; c < nch; ++c) {
-    const int L = min(FINAL_CHUNK, F.nblocks - c * FINAL_CHUNK);
-    const int cnt = min(max(L - w * 4 * WAVE, 0), 4 * WAVE);
+  // the top two levels over four quarter sums of a run of L values
+  auto top = [](const T* s4, const int L) {
+    T a = s4[0], b = s4[2];
+    if (4 * WAVE < L) a = a + s4[1];
+    if (12 * WAVE < L) b = b + s4[3];
+    if (8 * WAVE < L) a = a + b;
+    return a;
+  };
+  for (int c0 = 0; c0 < nch; c0 += CPR) {
+    const int c = c0 + w / 4;
+    const int L = c < nch ? min(FINAL_CHUNK, F.nblocks - c * FINAL_CHUNK) : 0;
+    const int cnt = min(max(L - q * 4 * WAVE, 0), 4 * WAVE);
 #pragma unroll
     for (int k = 0; k < VM_MAXRED; ++k) {
       if (k < F.n_red) {
-        const T* a = (const T*)F.partials[k] + (int64_t)c * FINAL_CHUNK + w * 4 * WAVE;
+        const T* a = (const T*)F.partials[k] + (int64_t)c * FINAL_CHUNK + q * 4 * WAVE;
         const T v = cnt > 0 ? block_tree(a, cnt, lane) : (T)0;
         if (lane == 0) fws[k][w] = v;
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < F.n_red) {
-      const int k = threadIdx.x;
-      T a = fws[k][0], b = fws[k][2];
-      if (4 * WAVE < L) a = a + fws[k][1];
-      if (12 * WAVE < L) b = b + fws[k][3];
-      if (8 * WAVE < L) a = a + b;
-      fcs[k][c] = a;
+    if ((int)threadIdx.x < F.n_red * CPR) {
+      const int k = threadIdx.x / CPR, j = threadIdx.x % CPR;
+      if (c0 + j < nch) fcs[k][c0 + j] = top(&fws[k][4 * j], min(FINAL_CHUNK, F.nblocks - (c0 + j) * FINAL_CHUNK));
     }
     __syncthreads();
   }
-  if (w < F.n_red) {
-    const T total = nch > 0 ? block_tree(fcs[w], nch, lane) : (T)0;
-    if (lane == 0) {
-      // (a vector load: the scalar cache must not keep the old value, which
-      // the pass may read again after this store)
-      T* res = (T*)F.result[w];
-      *res = F.init[w] ? total : *(volatile T*)res + total;
+  T total = (T)0;
+  int kr = -1;   // the reduction whose total this wave's lane 0 holds
+  if (nch <= 4 * WAVE) {
+    if (w < F.n_red) {
+      total = nch > 0 ? block_tree(fcs[w], nch, lane) : (T)0;
+      kr = w;
     }
+  } else if constexpr (MAXCH > 4 * WAVE) {
+    const int k = w / 4;
+    if (k < F.n_red) {
+      const int cnt = min(max(nch - q * 4 * WAVE, 0), 4 * WAVE);
+      const T v = cnt > 0 ? block_tree(fcs[k] + q * 4 * WAVE, cnt, lane) : (T)0;
+      if (lane == 0) fws[k][q] = v;
+    }
+    __syncthreads();
+    if (w < F.n_red) {
+      total = top(fws[w], nch);
+      kr = w;
+    }
+  }
+  if (kr >= 0 && lane == 0) {
+    // (a vector load: the scalar cache must not keep the old value, which a
+    // pass may read again after this store)
+    T* res = (T*)F.result[kr];
+    *res = F.init[kr] ? total : *(volatile T*)res + total;
   }
 }
 
@@ -735,7 +834,7 @@ void vm_kernel(const VmParams P) {
   // (P.fin), in place of the block-sum kernel's launch
   if constexpr (PG::COMPILED) {
     if (P.fin.n_red > 0) {
-      fin_sums<T>(P.fin);
+      fin_sums<T, BLOCK / WAVE, FIN_MAX_CHUNKS>(P.fin);
       __syncthreads();
     }
   }
@@ -861,8 +960,10 @@ void vm_kernel(const VmParams P) {
 #define DFX_C(f) (PG::COMPILED ? CP->f : P.f)
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= DFX_C(rows)) break;
+      // (realigned inputs read up to V elements either side of the strip)
       const bool interior = DFX_C(is1d) ? ((row0 + U) * TW <= DFX_C(n1d))
-                                        : (row0 + U <= DFX_C(rows) && cbase >= 0 && cbase + TW <= DFX_C(cols));
+                                        : (row0 + U <= DFX_C(rows) && cbase >= (PG::REALIGN ? V : 0) &&
+                                           cbase + TW + (PG::REALIGN ? V : 0) <= DFX_C(cols));
       int mode = MODE_FAST;
       unsigned vmask = (1u << E) - 1;
       if (!(DFX_C(unit_cols) && interior)) {
@@ -884,7 +985,8 @@ void vm_kernel(const VmParams P) {
         const int64_t nr = row0 + U;
         next_fast = r + U < r_hi && DFX_C(unit_cols) &&
                     (DFX_C(is1d) ? ((nr + U) * TW <= DFX_C(n1d))
-                                 : (nr + U <= DFX_C(rows) && cbase >= 0 && cbase + TW <= DFX_C(cols)));
+                                 : (nr + U <= DFX_C(rows) && cbase >= (PG::REALIGN ? V : 0) &&
+                                    cbase + TW + (PG::REALIGN ? V : 0) <= DFX_C(cols)));
       }
       if constexpr (PG::COMPILED) G.drow = r;
       vm_step<T, HV, SPMV, NR, NINB, SPLIT, ROWS, false, false, PG>(P, R0, R1, R2, R3, G, L, row0, c0, vmask, mode,

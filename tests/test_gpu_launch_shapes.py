@@ -2,9 +2,11 @@
 row_split (waves per tile of passes without reductions), col_shift (strips
 started early so that views misaligned alike access aligned vectors),
 red_split (compiled passes with one reduction: a block of four waves per
-tile, summands added in the canonical order) and fin_attach (a compiled
+tile, summands added in the canonical order), fin_attach (a compiled
 one-block pass reduces the block sums an earlier pass left, in place of the
-block-sum kernel).  Every workload runs with the shape on and with it off
+block-sum kernel) and realign (compiled passes whose outputs share one
+misalignment and inputs another: strips shifted for the outputs, inputs
+loaded as aligned vectors and shifted across lanes).  Every workload runs with the shape on and with it off
 and must give identical results; the misaligned views are also checked
 against numpy."""
 import numpy as np
@@ -17,7 +19,7 @@ from test_gpu_parity import cg_gpu, jacobi_gpu
 
 pytestmark = pytest.mark.gpu
 
-SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT", "DFX_FIN_ATTACH")
+SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT", "DFX_FIN_ATTACH", "DFX_REALIGN")
 
 
 def _runs(monkeypatch, fn, jit):
@@ -154,3 +156,42 @@ def test_fin_attach_many_blocks(monkeypatch, dtype, n):
     assert a_l == b_l - 1, (a_l, b_l)
     ref = float(np.sum(x.astype(np.float64) ** 2))
     assert abs(float(a_ss) - ref) <= (1e-10 if dtype == "f64" else 1e-4) * ref
+
+
+@pytest.mark.parametrize("dtype,cols,offs", [
+    ("f64", 1030, ((1, 1), (0, 0), (2, 2), (1, 3))),    # output 1 past a word, inputs 1, 1, 0
+    ("f32", 1032, ((1, 1), (0, 0), (2, 2), (1, 3))),    # output 1, inputs 3, 1, 2
+    ("f32", 1032, ((0, 2), (2, 1), (1, 3), (0, 0))),    # output 2, inputs 3, 1, 2
+])
+def test_realigned_inputs(monkeypatch, dtype, cols, offs):
+    """y[vo] = a[va] + b[vb] * c[vc] with the output view misaligned one way
+    and the inputs others, every pass compiled: realigned and plain runs give
+    the same bits, and numpy's."""
+    note("shapes realign %s offs=%s" % (dtype, offs))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    R = 70
+    h, w = R - 3, cols - 3
+    arrs = [synth.uniform(12, k, R * cols, -1.0, 1.0).astype(npdt).reshape(R, cols) for k in range(3)]
+
+    def run():
+        c = dfx.Context(device=0, window_size=8)
+        ha, hb, hc = (upload(c, x) for x in arrs)
+        hy = upload(c, np.zeros((R, cols), npdt))
+        vo, va, vb, vc = (c.part_tiling([h, w], list(o)) for o in offs)
+        T0 = c.part_tiling([h, w])
+        t = c.store_create([h, w], dtype)
+        c.submit("mul", [1, 1], [(hb, vb, "R"), (hc, vc, "R"), (t, T0, "W")])
+        c.submit("add", [1, 1], [(ha, va, "R"), (t, T0, "R"), (hy, vo, "W")])
+        c.store_release(t)
+        y = c.store_read(hy, [R, cols], dtype)
+        n = c.stats()["compiled_launches"]
+        c.close()
+        return y, n
+    res = _runs(monkeypatch, run, 2)
+    _same(res)
+    y, n = res[0][1]
+    assert n >= 1
+    sl = lambda x, o: x[o[0]:o[0] + h, o[1]:o[1] + w]
+    ey = np.zeros((R, cols), npdt)
+    ey[offs[0][0]:offs[0][0] + h, offs[0][1]:offs[0][1] + w] = sl(arrs[0], offs[1]) + sl(arrs[1], offs[2]) * sl(arrs[2], offs[3])
+    assert np.array_equal(y, ey)
