@@ -1238,10 +1238,18 @@ static void* g_dummy_stream = nullptr;  // zeroed 4 KB read by padding stream sl
 
 // Block sums a pass's workspace holds per reduction: one per block, or one
 // per tile when a compiled pass gives every tile its own block (red_split,
-// at most RED_SPLIT_MAX_TILES tiles).
+// at most RED_SPLIT_MAX_TILES tiles), or, for a one-tile pass with one
+// reduction, the tile's summands (red_split over several blocks).
 constexpr int64_t RED_SPLIT_MAX_TILES = 2048;
+// blocks of a one-tile reducing pass: 16 waves of two rows each (a multiple
+// of every kernel's rows per step), or for SpMV passes (one row per step)
+// 32 waves of one row; DFX_RED_GLOB=<n> sets the blocks (1, 2, 4 or 8; 0: off)
+constexpr int RED_SPLIT_BLOCKS = 4;
 static size_t block_sum_slots(const PassPlan& p) {
-  return (size_t)std::max<int64_t>(p.grid, p.n_tiles <= RED_SPLIT_MAX_TILES ? p.n_tiles : 0);
+  int64_t n = std::max<int64_t>(p.grid, p.n_tiles <= RED_SPLIT_MAX_TILES ? p.n_tiles : 0);
+  if (p.n_tiles == 1 && p.red_cstore.size() == 1)
+    n = std::max<int64_t>(n, (int64_t)RED_TH * (p.dtype == DFX_F64 ? Lanes<double>::TW : Lanes<float>::TW));
+  return (size_t)n;
 }
 
 static int ensure_workspace(Ctx& c, PassPlan& p) {
@@ -1695,10 +1703,34 @@ static int run_pass(Ctx& c, PassPlan& p, const std::vector<int64_t>& order) {
   // a compiled pass of one reduction and few tiles gives each tile a block
   // of four waves (red_split; bit-identical tile sums)
   if (fn && red_split_ok(p, P)) {
-    P.red_split = 1;
+    // a one-tile pass spreads its rows over RED_SPLIT_BLOCKS blocks (two
+    // rows per wave) and leaves the ordered sum of the summands to the
+    // block-sum reduction, which the next compiled one-block pass (the
+    // scalar task after a dot product) takes over (DFX_RED_GLOB=0: one block)
+    const char* rg = std::getenv("DFX_RED_GLOB");
+    int B = P.spmv ? 2 * RED_SPLIT_BLOCKS : RED_SPLIT_BLOCKS;
+    if (rg && (rg[0] == '0' || rg[0] == '1' || rg[0] == '2' || rg[0] == '4' || rg[0] == '8') && !rg[1])
+      B = rg[0] == '0' ? 1 : std::min(B, rg[0] - '0');
+    if (p.n_tiles != 1) B = 1;
+    P.red_split = B;
     P.sp_coop = 0;
-    P.grid = (int)p.n_tiles;
+    P.grid = (int)p.n_tiles * B;
     F.nblocks = (int)p.n_tiles;
+    if (B > 1) {
+      F.tile = 1;
+      F.nblocks = 0;
+      F.is1d = P.is1d;
+      F.col_shift = P.col_shift;
+      F.n1d = P.n1d;
+      F.rows = P.rows;
+      F.cols = P.cols;
+      if (P.red_direct) {
+        // the block-sum reduction now follows (count_launches assumed none)
+        P.red_direct = 0;
+        c.stats.launches += 1;
+        if (c.capturing) c.capture_launches += 1;
+      }
+    }
   }
   // Block sums an earlier pass left waiting: a compiled one-block pass of
   // the same element type reduces them first, in its own launch (the same

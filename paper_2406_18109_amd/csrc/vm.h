@@ -120,6 +120,12 @@ struct VmFinal {
   const void* partials[VM_MAXRED];
   void* result[VM_MAXRED];
   int32_t init[VM_MAXRED];
+  // tile: 1 when partials[0] holds the summands of a one-tile pass's single
+  // reduction (red_split over several blocks) at their places in the tile,
+  // to be added in the canonical order (valid elements of the tile's space:
+  // is1d, n1d, rows, cols, col_shift as in VmParams)
+  int32_t tile, is1d, col_shift;
+  int64_t n1d, rows, cols;
 };
 
 // Block sums a one-block compiled pass reduces before its own work (an
@@ -142,10 +148,13 @@ struct VmParams {
   // wave k of a tile taking rows [k, k + 1) * RED_TH / row_split.  No
   // reduction order is involved, so the split changes no bit.
   int32_t row_split;
-  // red_split (compiled passes with one reduction, one tile per block): the
-  // block's four waves take a quarter of its tile's rows each and stage the
-  // reduction's summands in dynamic LDS; wave 0 then adds them in the
-  // canonical order, so the tile sum has the bits of one wave's
+  // red_split (compiled passes with one reduction): B = red_split blocks
+  // per tile, whose 4B waves take RED_TH / 4B of its rows each and stage the
+  // reduction's summands (the values one wave would accumulate) at their
+  // places in the tile: with B = 1 in dynamic LDS, wave 0 then adding them
+  // in the canonical order, so the tile sum has the bits of one wave's; with
+  // B > 1 (a one-tile pass) in the block-sum workspace, added in the same
+  // order by the block-sum reduction (VmFinal.tile)
   int32_t red_split;
   // col_shift (2-D passes without reductions, 0 <= col_shift < V): strips
   // start col_shift columns early (strip s covers columns [s * TW -

@@ -674,6 +674,30 @@ template <typename T, int NW, int MAXCH> __device__ __forceinline__ void fin_sum
   __shared__ T fws[VM_MAXRED][NW];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (F.tile) {
+    // one tile's summands: wave 0 adds them lane by lane over the tile's
+    // rows, then columns (valid elements only), then across lanes, as the
+    // wave that owns a tile accumulates them
+    constexpr int V = Lanes<T>::V, TW = Lanes<T>::TW;
+    if (w != 0) return;
+    const T* ds = (const T*)F.partials[0];
+    const int64_t c0 = -(int64_t)F.col_shift + (int64_t)lane * V;
+    T acc = (T)0;
+    for (int r = 0; r < RED_TH; ++r) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int64_t col = c0 + v;
+        const bool ok = F.is1d ? (r * TW + col < F.n1d) : (r < F.rows && col >= 0 && col < F.cols);
+        if (ok) acc = acc + ds[r * TW + lane * V + v];
+      }
+    }
+    const T total = wave_sum(acc);
+    if (lane == 0) {
+      T* res = (T*)F.result[0];
+      *res = F.init[0] ? total : *(volatile T*)res + total;
+    }
+    return;
+  }
   const int q = w % 4;
   const int nch = (F.nblocks + FINAL_CHUNK - 1) / FINAL_CHUNK;
   // the top two levels over four quarter sums of a run of L values
@@ -907,10 +931,12 @@ void vm_kernel(const VmParams P) {
   // and its four waves take a quarter of the rows each)
   const int split = P.row_split > 1 ? P.row_split : 1;
   const bool rsplit = PG::COMPILED && P.red_split != 0;
-  const int64_t t_begin = rsplit ? (int64_t)lb : split > 1 ? gw / split : gw * P.tiles_per_wave;
+  const int rsb = rsplit ? P.red_split : 1;   // blocks per tile
+  const int64_t t_begin = rsplit ? (int64_t)(lb / rsb) : split > 1 ? gw / split : gw * P.tiles_per_wave;
   const int64_t t_end = min(t_begin + ((split > 1 || rsplit) ? 1 : P.tiles_per_wave), P.n_tiles);
-  const int r_lo = rsplit ? wib * (RED_TH / 4) : split > 1 ? (int)(gw % split) * (RED_TH / split) : 0;
-  const int r_hi = r_lo + (rsplit ? RED_TH / 4 : RED_TH / split);
+  const int r_lo = rsplit ? ((lb % rsb) * 4 + wib) * (RED_TH / (4 * rsb))
+                          : split > 1 ? (int)(gw % split) * (RED_TH / split) : 0;
+  const int r_hi = r_lo + (rsplit ? RED_TH / (4 * rsb) : RED_TH / split);
 
   // Arithmetic passes are stream-bound: their loads are software-pipelined
   // one step ahead inside a tile (up to four streams: the wider bucket would
@@ -941,7 +967,7 @@ void vm_kernel(const VmParams P) {
     G.acc0 = G.acc1 = G.acc2 = G.acc3 = (T)0;
     if constexpr (PG::COMPILED) {
       extern __shared__ __attribute__((aligned(16))) char vm_dyn_lds[];
-      G.dsum = rsplit ? (T*)vm_dyn_lds : nullptr;
+      G.dsum = !rsplit ? nullptr : rsb > 1 ? (T*)P.red_partials[0] : (T*)vm_dyn_lds;
     }
     bool have = false;  // L already holds this step's values (prefetched)
     bool staged = false;
@@ -1009,6 +1035,9 @@ void vm_kernel(const VmParams P) {
   if (P.n_red == 0) return;
   if constexpr (PG::COMPILED) {
     if (rsplit) {
+      // several blocks: the summands are in the workspace, for the
+      // block-sum reduction (VmFinal.tile)
+      if (rsb > 1) return;
       // the block's one tile: wave 0 adds the summands lane by lane over the
       // tile's rows, then columns (valid elements only), the order in which
       // one wave would have accumulated them; the tile sum is the block sum

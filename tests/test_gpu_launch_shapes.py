@@ -2,7 +2,8 @@
 row_split (waves per tile of passes without reductions), col_shift (strips
 started early so that views misaligned alike access aligned vectors),
 red_split (compiled passes with one reduction: a block of four waves per
-tile, summands added in the canonical order), fin_attach (a compiled
+tile, summands added in the canonical order; red_glob: a one-tile pass
+over four blocks, its summands added by the block-sum reduction), fin_attach (a compiled
 one-block pass reduces the block sums an earlier pass left, in place of the
 block-sum kernel) and realign (compiled passes whose outputs share one
 misalignment and inputs another: strips shifted for the outputs, inputs
@@ -19,7 +20,7 @@ from test_gpu_parity import cg_gpu, jacobi_gpu
 
 pytestmark = pytest.mark.gpu
 
-SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT", "DFX_FIN_ATTACH", "DFX_REALIGN")
+SWITCHES = ("DFX_ROW_SPLIT", "DFX_COL_SHIFT", "DFX_RED_SPLIT", "DFX_FIN_ATTACH", "DFX_REALIGN", "DFX_RED_GLOB")
 
 
 def _runs(monkeypatch, fn, jit):
