@@ -163,12 +163,14 @@ def test_gmg_compiled_bitwise(monkeypatch):
     assert na == 0 and nb > 0
 
 
-def test_graph_of_compiled_passes(monkeypatch):
+@pytest.mark.parametrize("m", [100, 64])
+def test_graph_of_compiled_passes(monkeypatch, m):
     """A CG iteration recorded as a graph after one eager (compiling)
-    iteration: three replays equal three eager interpreted iterations."""
-    note("jit cg graph")
+    iteration: three replays equal three eager interpreted iterations (64^2:
+    one-tile reducing passes over several blocks, their block-sum reduction
+    in the next scalar pass)."""
+    note("jit cg graph %d" % m)
     monkeypatch.delenv("DFX_JIT", raising=False)
-    m = 100
     rowptr, col, val = synth.poisson_csr(m, 2)
     b = synth.rhs(m * m, 4321)
     out = []
@@ -196,11 +198,14 @@ def test_graph_of_compiled_passes(monkeypatch):
     assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
 
 
-def test_noalloc_flush_compiled(monkeypatch):
-    """dfx_flush_noalloc runs compiled passes with the scratch array."""
-    note("jit noalloc flush cg 300")
+@pytest.mark.parametrize("m", [300, 64])
+def test_noalloc_flush_compiled(monkeypatch, m):
+    """dfx_flush_noalloc runs compiled passes with the scratch array (64^2:
+    one-tile reducing passes over several blocks, their summands in the
+    scratch array)."""
+    note("jit noalloc flush cg %d" % m)
     from test_zz_no_alloc import _cg
-    (_, rho_a, x_a), (_, rho_b, x_b) = _twice(monkeypatch, lambda: _cg(300, 5, True))
+    (_, rho_a, x_a), (_, rho_b, x_b) = _twice(monkeypatch, lambda: _cg(m, 5, True))
     assert rho_a == rho_b and np.array_equal(x_a, x_b)
 
 
