@@ -303,6 +303,12 @@ JitVariant jit_variant(int is_f64, int tier, int n_in, int spmv, int st_n, int r
   // FP32: 0.389 against 0.406 ms); FP64 ones do not (0.856 against 0.846 ms)
   const char* pf = std::getenv("DFX_JIT_PF");
   v.heavy_pf = (pf && (pf[0] == '0' || pf[0] == '1') && !pf[1]) ? pf[0] - '0' : (v.hv > 0 && !v.is_f64 ? 1 : 0);
+  // parameters reloaded at every step: yes, except in stencil-staged and
+  // realigning passes (set in jit_source), whose streaming steps measured
+  // faster with them kept live (the 8192^2 Jacobi sweep 0.4443 against
+  // 0.4472 ms; Black-Scholes FP64 0.862 against 0.844 ms the other way)
+  const char* rl = std::getenv("DFX_JIT_RELOAD");
+  v.reload = (rl && (rl[0] == '0' || rl[0] == '1') && !rl[1]) ? rl[0] - '0' : -1;
   return v;
 }
 
@@ -315,6 +321,10 @@ std::string jit_source(const JitVariant& v, const JitProgram& g, std::string* na
   s += "  static constexpr int WAVES = " + std::to_string(v.waves) + ";\n";
   s += std::string("  static constexpr bool HEAVY_PF = ") + (v.heavy_pf ? "true" : "false") + ";\n";
   s += "  static constexpr int N_IN = " + std::to_string(g.n_in) + ", N_OUT = " + std::to_string(g.n_out) + ";\n";
+  bool realigns = false;
+  for (int32_t d : g.realign) realigns = realigns || d != 0;
+  const bool reload = v.reload >= 0 ? v.reload != 0 : !(v.sten || realigns);
+  s += std::string("  static constexpr bool RELOAD = ") + (reload ? "true" : "false") + ";\n";
   s += "  static constexpr int out_reg[VM_MAXOUT] = " + int_list(g.out_reg, VM_MAXOUT) + ";\n";
   s += "  static constexpr int bc_reg[VM_MAXBC] = " + int_list(g.bc_reg, VM_MAXBC) + ";\n";
   s += "  static constexpr int st_on[VM_MAXIN] = " + int_list(g.st_on, VM_MAXIN) + ";\n";

@@ -39,6 +39,7 @@ struct JitVariant {
   int sten = 0;    // stencil staging variant
   int waves = 2;   // waves-per-SIMD target given to the compiler
   int heavy_pf = 0; // transcendental pass: load the next step during this one
+  int reload = -1;  // parameters reloaded at every step (step_params): 1, 0, -1 the default rule
 };
 
 // A pass's program: its instructions and register maps.
@@ -58,7 +59,8 @@ struct JitEntry;
 // step (their straight-line code keeps few registers that way, so more
 // waves are resident), and FP32 transcendental passes prefetch the next
 // step's loads.  DFX_JIT_ROWS (0, 1 or 2) and DFX_JIT_WAVES override the
-// choice for non-SpMV, unstaged passes, DFX_JIT_PF (0 or 1) the prefetch.
+// choice for non-SpMV, unstaged passes, DFX_JIT_PF (0 or 1) the prefetch,
+// DFX_JIT_RELOAD (0 or 1) whether parameters are reloaded at every step.
 JitVariant jit_variant(int is_f64, int tier, int n_in, int spmv, int st_n, int rows);
 
 // Source text of the pass's kernel and the name expression of its entry.

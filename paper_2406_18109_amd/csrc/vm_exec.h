@@ -175,6 +175,7 @@ __device__ __forceinline__ void vm_instr(typename GVec<T, GS>::type (&R0)[NR], t
 struct VmInterp {
   static constexpr bool COMPILED = false;
   static constexpr int N_IN = 0, N_OUT = 0;   // (compiled passes: the pass's stream counts)
+  static constexpr bool RELOAD = false;       // (compiled passes: parameters reloaded per step)
   static constexpr int WAVES = 1;
   static constexpr bool HEAVY_PF = false;   // transcendental passes prefetch the next step
   static constexpr int out_reg[VM_MAXOUT] = {};
@@ -233,7 +234,7 @@ __device__ __forceinline__ void spmv_rows(const VmParams& P, int64_t base, T (&o
 // load what it uses again, with scalar loads from the kernel-argument
 // segment.
 template <class PG> __device__ __forceinline__ const VmParams& step_params(const VmParams& P) {
-  if constexpr (PG::COMPILED) {
+  if constexpr (PG::COMPILED && PG::RELOAD) {
     typedef const __attribute__((address_space(4))) char* KB;
     int64_t off = 0;
     asm volatile("" : "+s"(off));
@@ -982,8 +983,8 @@ void vm_kernel(const VmParams P) {
       // the step's bounds (a compiled pass reads them again at every step;
       // the interpreter's are the kernel argument's, kept live)
       const VmParams* CP = nullptr;
-      if constexpr (PG::COMPILED) CP = &step_params<PG>(P);
-#define DFX_C(f) (PG::COMPILED ? CP->f : P.f)
+      if constexpr (PG::COMPILED && PG::RELOAD) CP = &step_params<PG>(P);
+#define DFX_C(f) (PG::COMPILED && PG::RELOAD ? CP->f : P.f)
       const int64_t row0 = tr * RED_TH + r;
       if (row0 >= DFX_C(rows)) break;
       // (realigned inputs read up to V elements either side of the strip)
