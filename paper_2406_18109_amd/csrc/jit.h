@@ -55,10 +55,10 @@ struct JitEntry;
 
 // The kernel variant of a compiled pass of `tier` with `n_in` streams, SpMV
 // prologue `spmv`, `st_n` staged streams and the planner's rows per step:
-// the interpreter's, except that transcendental passes take one row per
-// step (their straight-line code keeps few registers that way, so more
-// waves are resident), and FP32 transcendental passes prefetch the next
-// step's loads.  DFX_JIT_ROWS (0, 1 or 2) and DFX_JIT_WAVES override the
+// the interpreter's, except that FP32 transcendental passes take one row
+// per step (their straight-line code keeps few registers that way, so more
+// waves are resident) and prefetch the next step's loads, and FP64 ones
+// take two.  DFX_JIT_ROWS (0, 1 or 2) and DFX_JIT_WAVES override the
 // choice for non-SpMV, unstaged passes, DFX_JIT_PF (0 or 1) the prefetch,
 // DFX_JIT_RELOAD (0 or 1) whether parameters are reloaded at every step.
 JitVariant jit_variant(int is_f64, int tier, int n_in, int spmv, int st_n, int rows);
