@@ -288,7 +288,7 @@ int dfx_plan_cache_load(dfx_ctx* ctx, const char* path, int64_t* n_loaded);
  * variable), stored there as code objects and reused by later processes.
  * A kernel that fails to compile or load leaves its pass interpreted.
  * Which passes run compiled (measured on MI355X): those with transcendental
- * ops, those of fewer than 256 tiles (latency-bound) and stencil-staged ones;
+ * ops, those of fewer than 1024 tiles (latency-bound) and stencil-staged ones;
  * large arithmetic and SpMV passes stream as fast interpreted and stay so.
  * DFX_JIT_ALL=1 compiles every pass. */
 typedef struct {

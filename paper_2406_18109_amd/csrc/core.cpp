@@ -1439,8 +1439,10 @@ static int row_split_for(const PassPlan& p, const VmParams& P) {
 // Passes that run compiled when jit is on (measured on MI355X):
 // transcendental passes, where the interpreter's dispatch dominates
 // (Black-Scholes FP64 over 2^26 options: 0.79 against 1.05 ms); small
-// passes of fewer than 256 tiles, which are latency-bound (CG 64^2: 0.074
-// against 0.100 ms per iteration); stencil-staged passes (the 8192^2 Jacobi
+// passes of fewer than 1024 tiles, which are latency-bound (CG 64^2: 0.074
+// against 0.100 ms per iteration; the GMG 1023^2 iteration, whose fine-level
+// passes have 256 tiles: 0.82 ms with them compiled against 0.97 ms with the
+// limit at 256; 4096 gave 0.82 ms as well); stencil-staged passes (the 8192^2 Jacobi
 // sweep: 0.46 against 0.51 ms).  Large arithmetic and staged-SpMV passes
 // stream at the interpreter's rate or slightly below it compiled (the CG
 // 256^3 SpMV + dot: 438 against 390 us) and stay interpreted.
@@ -1448,7 +1450,7 @@ static int row_split_for(const PassPlan& p, const VmParams& P) {
 static bool jit_wanted(const PassPlan& p, int st_n) {
   const char* all = std::getenv("DFX_JIT_ALL");
   if (all && all[0] == '1') return true;
-  int64_t small = 256;
+  int64_t small = 1024;
   if (const char* e = std::getenv("DFX_JIT_SMALL")) small = std::atoll(e);
   return p.tier != TIER_ARITH || p.n_tiles < small || st_n > 0;
 }
